@@ -1,0 +1,394 @@
+"""Pins of the FP64 CPU oracle against things other than itself: exact
+rationals, closed forms, Kronecker-built dense operators, dense
+eigendecomposition, symmetry and translation invariants (CPU only)."""
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import _dense as D
+from oracle import oracle as O
+from paper_2006_03697_amd import workloads as W
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+
+def _solve_fraction(A, b):
+    """Exact Gauss-Jordan elimination over the rationals."""
+    n = len(b)
+    M = [list(map(Fraction, A[i])) + [Fraction(b[i])] for i in range(n)]
+    for col in range(n):
+        piv = next(r for r in range(col, n) if M[r][col] != 0)
+        M[col], M[piv] = M[piv], M[col]
+        pv = M[col][col]
+        M[col] = [x / pv for x in M[col]]
+        for r in range(n):
+            if r != col and M[r][col] != 0:
+                f = M[r][col]
+                M[r] = [a - f * bb for a, bb in zip(M[r], M[col])]
+    return [M[i][n] for i in range(n)]
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    cell = W.tiny_cell()
+    return cell, O.OracleCell(cell)
+
+
+@pytest.fixture(scope="module")
+def tiny_run():
+    return O.run(W.tiny_cell())
+
+
+def _sample(oc, k, seed=7):
+    return W.node_sample(oc.Nd, k, seed)
+
+
+def _node_q3(oc, q):
+    n0, n1 = oc.n[0], oc.n[1]
+    return np.array([q % n0, (q // n0) % n1, q // (n0 * n1)])
+
+
+def _dense_cube(oc, q):
+    """Dense H_q, gradient matrices, coordinates and projector columns of
+    node q assembled from 1D matrices (independent of the oracle's loops)."""
+    m, nc, h = oc.m, oc.nc, oc.h
+    q3 = _node_q3(oc, q)
+    lap = sum(D.kron3(D.fd_1d(nc, oc.c2, False), a, nc) for a in range(3))
+    G = [D.kron3(D.fd_1d(nc, oc.c1, True), a, nc) / h for a in range(3)]
+    a = np.arange(-m, m + 1)
+    idx = [(q3[ax] + a) % oc.n[ax] for ax in range(3)]
+    IX, IY, IZ = np.meshgrid(idx[0], idx[1], idx[2], indexing="ij")
+    node = IX + oc.n[0] * (IY + oc.n[1] * IZ)
+    V = oc.vloc[node.transpose(2, 1, 0).ravel()]
+    coords = D.cube_coords(q3, m, h)
+    sp = oc.cell["species_params"][0]
+    X, cen = D.projectors(coords, oc.img, sp["p_sigma"], sp["p_rcut"])
+    gdv = sp["gamma"] * oc.dV
+    H = -0.5 / h ** 2 * lap + np.diag(V) + gdv * X.T @ X
+    return dict(H=H, G=G, coords=coords, X=X, cen=cen, gdv=gdv, ctr=(nc ** 3) // 2, q3=q3)
+
+
+def _cheb_poly(c, x):
+    """sum'_j c_j T_j(x) for x (any real): T_j through the recurrence."""
+    t0 = np.ones_like(x)
+    t1 = x.copy()
+    s = 0.5 * c[0] * t0 + (c[1] * t1 if len(c) > 1 else 0.0)
+    for j in range(2, len(c)):
+        t0, t1 = t1, 2 * x * t1 - t0
+        s = s + c[j] * t1
+    return s
+
+
+# ----------------------------------------------------------------------------
+# finite differences (12th order, Sec. V)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M", [1, 2, 3, 6])
+def test_fd_weights_are_the_exact_central_rules(M):
+    c2, c1 = O.fd_weights(M)
+    # second derivative: exact on x^p for p = 0, 2, ..., 2M (odd p by symmetry)
+    A = [[1] + [2 * k ** p for k in range(1, M + 1)] if p == 0 else
+         [0] + [2 * k ** p for k in range(1, M + 1)] for p in range(0, 2 * M + 1, 2)]
+    b = [0] * (M + 1)
+    b[1] = 2
+    exact2 = _solve_fraction(A, b)
+    np.testing.assert_allclose(c2, [float(x) for x in exact2], rtol=2e-16, atol=0)
+    # first derivative: exact on x^p for p = 1, 3, ..., 2M-1
+    A1 = [[2 * k ** p for k in range(1, M + 1)] for p in range(1, 2 * M, 2)]
+    b1 = [1] + [0] * (M - 1)
+    exact1 = _solve_fraction(A1, b1)
+    np.testing.assert_allclose(c1[1:], [float(x) for x in exact1], rtol=2e-16, atol=0)
+
+
+def test_fd_symbol_maximum_is_gershgorin():
+    c2, _ = O.fd_weights(6)
+    th = np.linspace(0, np.pi, 20001)
+    sym = -(c2[0] + 2 * sum(c2[k] * np.cos(k * th) for k in range(1, 7)))
+    assert abs(sym.max() - (abs(c2[0]) + 2 * np.abs(c2[1:]).sum())) < 1e-12
+    assert abs(sym[-1] - sym.max()) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# local potential and projectors (synthetic species)
+# ----------------------------------------------------------------------------
+
+def _gauss_tail(t):
+    """Fraction of a 3D Gaussian's mass beyond t standard deviations."""
+    return special.erfc(t / math.sqrt(2)) + math.sqrt(2 / math.pi) * t * math.exp(-t * t / 2)
+
+
+def test_vloc_integrates_to_the_gaussian_mass():
+    cell = W.random_cell(seed=5, L=6.0, h=0.3, n_atoms=3, d_min=2.0, rcut=1.0, npl=4, kT=0.1)
+    oc = O.OracleCell(cell)
+    sp = cell["species_params"][0]
+    s, A, rc = sp["v_sigma"], sp["v_amp"], sp["v_rcut"]
+    expect = -A * (2 * math.pi * s * s) ** 1.5 * (1 - _gauss_tail(rc / s)) * 3
+    got = oc.vloc.sum() * oc.dV
+    assert abs(got - expect) < 1e-7 * abs(expect)
+
+
+def test_projector_sums_match_the_gaussian_mass():
+    cell = W.make_cell(6.0, 0.3, [[3.0 + 0.07, 3.0 - 0.11, 3.0 + 0.05]], rcut=4.2, npl=4, kT=0.1)
+    oc = O.OracleCell(cell)
+    q = 10 + 20 * (10 + 20 * 10)
+    img, sums = oc.projector_sums(q)
+    sp = cell["species_params"][0]
+    s, rp = sp["p_sigma"], sp["p_rcut"]
+    full = (2 * math.pi * s * s) ** 1.5 * (1 - _gauss_tail(rp / s)) / oc.dV
+    # the image of the atom itself lies entirely in the 29^3 cube
+    R = oc.img[img]
+    k = int(np.argmin(np.linalg.norm(R - np.array([3.07, 2.89, 3.05]), axis=1)))
+    assert abs(sums[k] - full) < 1e-8 * full
+
+
+def test_vloc_is_periodic_under_grid_translation(tiny):
+    cell, oc = tiny
+    shift = np.array([2, 1, 3])
+    c2 = dict(cell)
+    c2["pos"] = cell["pos"] + shift * cell["h"]
+    oc2 = O.OracleCell(c2)
+    v1 = oc.vloc.reshape(oc.n[2], oc.n[1], oc.n[0])
+    v2 = oc2.vloc.reshape(oc.n[2], oc.n[1], oc.n[0])
+    rolled = np.roll(v1, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    assert np.max(np.abs(rolled - v2)) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# nodal Hamiltonian, Lanczos bounds, Chebyshev moments (Sec. IV)
+# ----------------------------------------------------------------------------
+
+def test_nodal_hamiltonian_matches_kronecker_assembly(tiny):
+    cell, oc = tiny
+    for q in _sample(oc, 4):
+        H = oc.dense_H(q)
+        ref = _dense_cube(oc, q)["H"]
+        assert np.max(np.abs(H - ref)) < 1e-12 * np.max(np.abs(ref))
+        assert np.max(np.abs(H - H.T)) < 1e-12 * np.max(np.abs(H))
+
+
+def test_lanczos_bounds_contain_the_spectrum(tiny):
+    cell, oc = tiny
+    nodes = _sample(oc, 12, seed=11)
+    lo, hi, chi, zeta = oc.bounds(nodes)
+    al, be, st = oc.lanczos(nodes)
+    for i, q in enumerate(nodes):
+        H = oc.dense_H(q)
+        ev = np.linalg.eigvalsh(H)
+        ctr = H.shape[0] // 2
+        assert abs(al[i, 0] - H[ctr, ctr]) < 1e-12 * abs(H[ctr, ctr])
+        assert lo[i] <= ev[0] + 1e-10
+        assert hi[i] >= ev[-1] - 1e-10
+        # bounds are tight enough to be useful
+        assert hi[i] - lo[i] < 1.2 * (ev[-1] - ev[0])
+
+
+def test_chebyshev_moments_match_dense_eigendecomposition(tiny):
+    cell, oc = tiny
+    nodes = _sample(oc, 6, seed=3)
+    lo, hi, chi, zeta = oc.bounds(nodes)
+    mom = oc.moments(nodes, chi, zeta)
+    for i, q in enumerate(nodes):
+        ev, U = np.linalg.eigh(oc.dense_H(q))
+        w = U[U.shape[0] // 2, :] ** 2
+        xh = (ev - chi[i]) / zeta[i]
+        T0, T1 = np.ones_like(xh), xh.copy()
+        ref = [w.sum(), (w * xh).sum()]
+        for j in range(2, oc.npl + 1):
+            T0, T1 = T1, 2 * xh * T1 - T0
+            ref.append((w * T1).sum())
+        np.testing.assert_allclose(mom[i], ref, rtol=0, atol=1e-12)
+
+
+def test_first_moments_and_boundedness(tiny):
+    cell, oc = tiny
+    nodes = _sample(oc, 5, seed=9)
+    lo, hi, chi, zeta = oc.bounds(nodes)
+    mom = oc.moments(nodes, chi, zeta)
+    for i, q in enumerate(nodes):
+        H = oc.dense_H(q)
+        c = H.shape[0] // 2
+        e = np.zeros(H.shape[0])
+        e[c] = 1.0
+        He = (H @ e - chi[i] * e) / zeta[i]
+        assert mom[i, 0] == 1.0
+        assert abs(mom[i, 1] - He[c]) < 1e-14
+        assert abs(mom[i, 2] - (2 * He @ He - 1)) < 1e-13
+    assert np.all(np.abs(mom) <= 1 + 1e-12)
+
+
+# ----------------------------------------------------------------------------
+# Clenshaw-Curtis Fermi-Dirac coefficients (Sec. IV, App. A)
+# ----------------------------------------------------------------------------
+
+def test_coefficients_symmetric_fermi_level():
+    # g(x) + g(-x) = 1 when mu_hat = 0: c_0 = 1 and every other even c vanishes
+    c, d = O.cheb_coeffs(0.0, 4e-3, O.quad_points(1.0, 4e-3, 40), 40)
+    assert abs(c[0] - 1.0) < 1e-15
+    assert np.max(np.abs(c[2::2])) < 1e-15
+
+
+@pytest.mark.parametrize("sig", [5e-3, 1.5e-3])
+def test_coefficients_match_adaptive_quadrature(sig):
+    mu = 0.13
+    M = O.quad_points(1.0, sig, 60)
+    c, d = O.cheb_coeffs(mu, sig, M, 60)
+    th0 = math.acos(mu)
+    for j in [0, 1, 7, 24, 60]:
+        f = lambda t: O.fermi(math.cos(t), mu, sig) * math.cos(j * t)
+        pts = [th0 + k * sig for k in range(-60, 61, 4)]
+        val = integrate.quad(f, 0, math.pi, points=[p for p in pts if 0 < p < math.pi],
+                             limit=500, epsabs=1e-16, epsrel=1e-14)[0]
+        assert abs(c[j] - 2 / math.pi * val) < 5e-14
+        fd = lambda t: math.cos(t) * O.fermi(math.cos(t), mu, sig) * math.cos(j * t)
+        vald = integrate.quad(fd, 0, math.pi, points=[p for p in pts if 0 < p < math.pi],
+                              limit=500, epsabs=1e-16, epsrel=1e-14)[0]
+        assert abs(d[j] - 2 / math.pi * vald) < 5e-14
+
+
+def test_band_energy_coefficients_satisfy_the_product_rule():
+    # x T_j = (T_{j+1} + T_{|j-1|}) / 2  =>  d_j = (c_{j+1} + c_{|j-1|}) / 2
+    c, d = O.cheb_coeffs(-0.2, 2e-3, O.quad_points(1.0, 2e-3, 30), 31)
+    for j in range(0, 31):
+        assert abs(d[j] - 0.5 * (c[j + 1] + c[abs(j - 1)])) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# density matrix column, density, band energy, stress
+# ----------------------------------------------------------------------------
+
+def _dense_column(oc, q, chi, zeta, coef):
+    ev, U = np.linalg.eigh(oc.dense_H(q))
+    c = U.shape[0] // 2
+    p = _cheb_poly(coef, (ev - chi) / zeta)
+    return U @ (p * U[c, :])
+
+
+def test_dm_column_matches_dense_polynomial(tiny):
+    cell, oc = tiny
+    mu = 0.25
+    for q in _sample(oc, 3, seed=21):
+        lo, hi, chi, zeta = oc.bounds([q])
+        c, _ = O.node_coefficients(oc, mu, chi, zeta)
+        d, _ = oc.dm_column(q, chi[0], zeta[0], c[0])
+        ref = _dense_column(oc, q, chi[0], zeta[0], c[0])
+        assert np.max(np.abs(d - ref)) < 1e-13
+
+
+def test_dm_column_converges_to_the_fermi_operator_with_degree():
+    mu = 0.25
+    errs = []
+    for npl in [24, 50, 100, 200]:
+        cell = W.tiny_cell(npl=npl)
+        oc = O.OracleCell(cell)
+        q = 1000
+        lo, hi, chi, zeta = oc.bounds([q])
+        c, _ = O.node_coefficients(oc, mu, chi, zeta)
+        d, _ = oc.dm_column(q, chi[0], zeta[0], c[0])
+        ev, U = np.linalg.eigh(oc.dense_H(q))
+        f = 0.5 * (1 - np.tanh((ev - mu) / (2 * oc.kT)))
+        exact = U @ (f * U[U.shape[0] // 2, :])
+        errs.append(np.max(np.abs(d - exact)))
+    # exponential convergence (Sec. V.A) down to the rounding floor
+    assert all(b < 0.1 * a for a, b in zip(errs[:2], errs[1:3]))
+    assert errs[-1] < 1e-15
+    assert errs[0] > 1e-6       # degree 24 is not converged at this kT
+
+
+def test_electron_count_and_density(tiny_run):
+    r = tiny_run
+    assert abs(r["n_count"] - 2.0) < 1e-12 * 2.0
+    assert np.all(r["rho"] > 0)
+
+
+def test_band_energy_per_node_matches_dense(tiny, tiny_run):
+    cell, oc = tiny
+    r = tiny_run
+    for q in _sample(oc, 3, seed=5):
+        i = int(q)
+        ev, U = np.linalg.eigh(oc.dense_H(q))
+        w = U[U.shape[0] // 2, :] ** 2
+        xh = (ev - r["chi"][i]) / r["zeta"][i]
+        pc = _cheb_poly(r["coef"][i], xh)
+        pd = _cheb_poly(r["dcoef"][i], xh)
+        ref = 2 * np.sum(w * (r["chi"][i] * pc + r["zeta"][i] * pd))
+        assert abs(r["e_node"][i] - ref) < 1e-12 * max(1.0, abs(ref))
+        assert abs(r["rho"][i] - 2 / oc.dV * np.sum(w * pc)) < 1e-12 * r["rho"][i]
+
+
+def test_stress_functionals_match_dense_operators(tiny, tiny_run):
+    cell, oc = tiny
+    r = tiny_run
+    for q in _sample(oc, 4, seed=13):
+        i = int(q)
+        dc = _dense_cube(oc, q)
+        d = _dense_column(oc, q, r["chi"][i], r["zeta"][i], r["coef"][i])
+        G, ctr = dc["G"], dc["ctr"]
+        K = np.array([[2 * (G[a] @ (G[b] @ d))[ctr] for b in range(3)] for a in range(3)])
+        N = np.zeros((3, 3))
+        for X, R in zip(dc["X"], dc["cen"]):
+            if X[ctr] == 0.0:
+                continue
+            s = X @ d
+            for a in range(3):
+                ga = G[a] @ d
+                for b in range(3):
+                    g = np.sum(X * (dc["coords"][:, b] - R[b]) * ga)
+                    N[a, b] += -2 * dc["gdv"] * X[ctr] * ((s if a == b else 0.0) + 2 * g)
+        rec = r["records"][i]
+        scale = np.max(np.abs(K)) + np.max(np.abs(N))
+        assert np.max(np.abs(rec[2:11].reshape(3, 3) - K)) < 1e-11 * scale
+        assert np.max(np.abs(rec[11:20].reshape(3, 3) - N)) < 1e-11 * scale
+
+
+def test_kinetic_stress_is_symmetric_per_node(tiny_run):
+    K = tiny_run["records"][:, 2:11].reshape(-1, 3, 3)
+    assert np.max(np.abs(K - K.transpose(0, 2, 1))) < 1e-13 * np.max(np.abs(K))
+
+
+def test_kinetic_stress_is_negative_once_converged():
+    cell = W.tiny_cell(npl=160)
+    r = O.run(cell, nodes=W.node_sample(1728, 60, 2), mu=0.25)
+    K = r["records"][:, 2:11].sum(0).reshape(3, 3)
+    assert np.all(np.linalg.eigvalsh(0.5 * (K + K.T)) < 0)
+
+
+def test_zero_projector_energy_gives_zero_nonlocal_stress():
+    cell = W.tiny_cell()
+    cell["species_params"][0]["gamma"] = 0.0
+    r = O.run(cell, nodes=W.node_sample(1728, 40, 3), mu=0.25)
+    assert np.all(r["records"][:, 11:20] == 0.0)
+    assert np.all(r["e_nl_node"] == 0.0)
+
+
+def test_single_atom_on_a_node_gives_isotropic_stress():
+    cell = W.make_cell(6.0, 0.5, [[3.0, 3.0, 3.0]], rcut=2.0, npl=24, kT=0.1)
+    r = O.run(cell)
+    s = r["sigma_full"]
+    scale = np.max(np.abs(s))
+    assert abs(s[0, 0] - s[1, 1]) < 1e-12 * scale and abs(s[1, 1] - s[2, 2]) < 1e-12 * scale
+    off = s - np.diag(np.diag(s))
+    assert np.max(np.abs(off)) < 1e-12 * scale
+    parts = r["parts"]
+    assert np.max(np.abs(parts[9:].reshape(3, 3) - np.diag(np.diag(parts[9:].reshape(3, 3))))) \
+        < 1e-12 * np.max(np.abs(parts[9:]))
+
+
+def test_translation_by_a_grid_vector(tiny_run):
+    cell = W.tiny_cell()
+    shift = np.array([2, 1, 3])
+    cell["pos"] = cell["pos"] + shift * cell["h"]
+    r2 = O.run(cell)
+    r1 = tiny_run
+    n = 12
+    rho1 = r1["rho"].reshape(n, n, n)
+    rho2 = r2["rho"].reshape(n, n, n)
+    rolled = np.roll(rho1, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    assert np.max(np.abs(rolled - rho2)) < 1e-10 * np.max(rho1)
+    assert abs(r1["e_band"] - r2["e_band"]) < 1e-11 * abs(r1["e_band"])
+    assert np.max(np.abs(r1["sigma_voigt"] - r2["sigma_voigt"])) < 1e-10 * np.max(np.abs(r1["sigma_voigt"]))
