@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""SQ node-columns/s including stress, FP64 and mixed precision, on one MI355X.
+
+A step is one pass of the whole hot path over one cell already resident in
+HBM: spectral bounds (FP64 Lanczos), Chebyshev moments, Fermi level,
+Clenshaw-Curtis coefficients and density (sq_density), band energy
+(sq_energy) and the kinetic + nonlocal stress pass (sq_stress).  The plan
+(grid, atom images, local potential, capacity census) is built before the
+timed region.  Default workload: the 64000-node cell (16 Bohr cube, h = 0.4,
+64 atoms, 21^3 cubes, degree 60, kT = 0.05 Ha).
+
+Prints one JSON line.  value = node-columns/s of the FP64 path; the mixed
+path (FP32 recurrence vectors, FP64 accumulation) is reported beside it.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SQ node-columns/sec incl. stress, FP64 vs mixed precision; % HBM roofline"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x FMA (2 flop) x 2.4 GHz.  FP64 vector
+# FMAs and unpacked FP32 FMAs issue at the same rate (packed FP32 is not used).
+PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBPS = 8000.0
+
+# Algorithmic FLOPs of one application of the scaled nodal operator, per cube
+# node: 37-point 12th-order stencil (37 multiply-adds), local potential
+# (1 multiply-add), scale and previous-vector subtraction (2 flops); per
+# (node, projector) pair: projection and projector term (2 multiply-adds).
+F_POINT = 2 * 37 + 2 + 2
+F_PAIR = 4
+
+
+def kernel_flops(info, K):
+    """Algorithmic FLOPs of the three recurrence kernels for one cell."""
+    Nd, nc, npl, pairs = int(info[0]), int(info[1]), int(info[2]), int(info[8])
+    pts = Nd * nc ** 3
+    return {
+        "lanczos": K * ((F_POINT + 8) * pts + F_PAIR * pairs),
+        "moments": ((npl + 1) // 2) * ((F_POINT + 4) * pts + F_PAIR * pairs),
+        "stress": npl * ((F_POINT + 2) * pts + F_PAIR * pairs),
+    }
+
+
+def hbm_bytes(info, K):
+    """Algorithmic HBM traffic of one step (bytes): the local potential read
+    by every node's cube (once per kernel pass, L2-resident in practice is
+    not assumed), moments written and read, coefficients, records."""
+    Nd, nc, npl = int(info[0]), int(info[1]), int(info[2])
+    v = 8 * Nd * 3                     # potential column reads (three passes), per node column
+    mom = 8 * Nd * (npl + 1) * 2       # moments written, read by coefficients
+    coef = 8 * Nd * (npl + 1) * 2      # coefficients written, read by the stress pass
+    lan = 8 * Nd * 2 * K               # Lanczos tridiagonals
+    rec = 8 * Nd * 20                  # per-node records
+    return v + mom + coef + lan + rec
+
+
+def run_precision(sq, cell, precision, steps, warmup):
+    import torch
+    t0 = time.time()
+    plan = sq.Plan([cell], precision=precision)
+    setup_s = time.time() - t0
+    info = plan.info[0]
+
+    def step():
+        plan.density_only(0)
+        plan.energy(0)
+        plan.stress(0)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.phase_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph = plan.phase_times(reset=True)
+    _, mu = plan.density(0)
+    sig, _ = plan.stress(0)
+    plan.close()
+    ms = (t1 - t0) * 1000.0 / steps
+    return dict(ms=ms, setup_s=setup_s, info=info, phases=ph, mu=float(mu[0]),
+                sigma=[float(x) for x in sig[0]])
+
+
+def cpu_baseline(cell, mu, sample):
+    """The oracle as it stands, on a bounded sample of the cell's nodes at the
+    GPU's Fermi level: bounds, moments, coefficients, stress pass."""
+    from oracle import oracle as O
+    from paper_2006_03697_amd import workloads as W
+    n = int(round(cell["L"][0] / cell["h"]) * round(cell["L"][1] / cell["h"]) *
+            round(cell["L"][2] / cell["h"]))
+    nodes = W.node_sample(n, sample, seed=7)
+    O.run(cell, nodes=nodes[:4], mu=mu)           # build + load the C core
+    t0 = time.perf_counter()
+    O.run(cell, nodes=nodes, mu=mu)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return dict(value=len(nodes) / dt, unit="node-columns/s", cores=cores, kind="oracle",
+                sample="%d of %d nodes of the same cell (seed 7), full per-node path at the "
+                       "GPU's Fermi level, %.1f s" % (len(nodes), n, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=1536,
+                    help="nodes in the oracle's CPU-baseline sample (0: skip)")
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; a multi-GPU run (%d) is not part of it"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2006_03697_amd import sq
+    from paper_2006_03697_amd import workloads as W
+    sq.load()
+    cell = W.fp64_cell()
+    K = int(cell["lanczos_steps"])
+    res = {}
+    for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
+        res[prec] = run_precision(sq, cell, prec, args.steps, args.warmup)
+        print("bench: %s %.2f ms/step  phases %s" % (
+            prec, res[prec]["ms"], {k: round(v[0] / max(v[1], 1), 3) for k, v in res[prec]["phases"].items()}),
+            file=sys.stderr, flush=True)
+
+    head = "fp64" if "fp64" in res else "mixed"
+    r = res[head]
+    info = r["info"]
+    Nd = int(info[0])
+    flops = kernel_flops(info, K)
+    per_launch = {k: r["phases"][k][0] / max(r["phases"][k][1], 1) for k in flops}
+    dom = max(per_launch, key=lambda k: per_launch[k])
+    achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
+    step_bytes = hbm_bytes(info, K)
+    out = {
+        "metric": METRIC,
+        "value": Nd / (r["ms"] * 1e-3),
+        "unit": "node-columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "periodic 16 Bohr cube, h 0.4 (40^3 = 64000 nodes), 64 atoms "
+                               "(seed 1, min spacing 1.5), R_cut 4 (21^3 cubes), degree 60, "
+                               "kT 0.05 Ha, 12th-order FD, Lanczos K=%d" % K,
+                   "nodes": Nd, "cube": int(info[1]) ** 3, "npl": int(info[2]),
+                   "precision": head},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None},
+        "hbm": {"achieved": step_bytes / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
+                "unit": "GB/s", "frac": step_bytes / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS},
+        "phases_ms": {k: v[0] / max(v[1], 1) for k, v in r["phases"].items()},
+        "setup_s": r["setup_s"],
+    }
+    if "mixed" in res and head == "fp64":
+        m = res["mixed"]
+        mf = kernel_flops(m["info"], K)
+        mpl = {k: m["phases"][k][0] / max(m["phases"][k][1], 1) for k in mf}
+        out["mixed"] = {"value": Nd / (m["ms"] * 1e-3), "ms_per_step": m["ms"], "dtype": "f32+f64",
+                        "speedup_vs_fp64": r["ms"] / m["ms"],
+                        "phases_ms": {k: v[0] / max(v[1], 1) for k, v in m["phases"].items()},
+                        "stress_tflops": mf["stress"] / (mpl["stress"] * 1e-3) / 1e12,
+                        "sigma_diff_vs_fp64": max(abs(a - b) for a, b in zip(m["sigma"], r["sigma"]))}
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(cell, r["mu"], args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

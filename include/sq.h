@@ -1,0 +1,162 @@
+/*
+ * sq.h -- C ABI of the MI355X (gfx950) infinite-cell Clenshaw-Curtis
+ * Spectral Quadrature (SQ) hot path.
+ *
+ * Operation (Sharma, Hamel, Bethkenhagen, Pask, Suryanarayana, arXiv
+ * 2006.03697, Sec. IV and App. A): for every finite-difference node q of an
+ * orthorhombic periodic cell, the nodal Hamiltonian H_q (the Hamiltonian
+ * restricted to the cube of side 2 R_cut centred at q: 12th-order FD
+ * Laplacian, local potential, atom-centred nonlocal projectors of every atom
+ * image in R^3) is scaled to Hhat_q = (H_q - chi_q)/zeta_q from its extreme
+ * eigenvalues; the Chebyshev three-term recurrence t^{j+1} = 2 Hhat t^j -
+ * t^{j-1} from the unit vector w_q, weighted by the Clenshaw-Curtis
+ * Fermi-Dirac coefficients c_q^j, gives the density-matrix column
+ * d_q = sum' c_q^j t^j, from which the electron density
+ * rho_q = (2/dV) sum' c_q^j rho_q^j, the band energy
+ * 2 sum_q sum' (chi_q c_q^j + zeta_q d_q^j) rho_q^j and the kinetic and
+ * nonlocal density-matrix stress follow.
+ *
+ * Units: Hartree atomic units (Ha, Bohr).  All host-side scalars and arrays
+ * are IEEE binary64 unless stated otherwise.
+ *
+ * Conventions: node i = ix + n0 (iy + n1 iz) at position h (ix, iy, iz);
+ * Voigt order (11, 22, 33, 23, 13, 12); 3x3 blocks row-major (alpha, beta).
+ *
+ * Ownership: sq_setup copies every input, so the caller may free its
+ * arrays on return.  The plan owns all device memory it allocates (through
+ * the caller's allocator when one is given, else hipMalloc) and releases it
+ * in sq_destroy.  Output buffers are owned by the caller.
+ *
+ * Errors: every entry point returns a status; nothing aborts across the
+ * ABI.  On error the outputs are left untouched and sq_last_error() holds a
+ * message.  A plan is used from one host thread at a time; separate plans
+ * are independent.  Work is enqueued on the stream given at setup and every
+ * call returns after that stream has finished the call's work.
+ */
+#ifndef SQ_H
+#define SQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sq_plan_s* sq_plan;
+
+typedef enum {
+  SQ_OK = 0,
+  SQ_E_ARG = 1,     /* invalid argument (shape, range, capacity)            */
+  SQ_E_ALLOC = 2,   /* device allocation failed                              */
+  SQ_E_DEVICE = 3,  /* HIP runtime error                                     */
+  SQ_E_BOUNDS = 4,  /* a Chebyshev moment left [-1, 1]: spectral bounds bad  */
+  SQ_E_NOCONV = 5,  /* Fermi level not bracketed / not found                 */
+  SQ_E_STATE = 6    /* call order violated (e.g. stress before density)     */
+} sq_status;
+
+typedef enum { SQ_FP64 = 0, SQ_MIXED = 1 } sq_precision;
+typedef enum { SQ_MU_SOLVE = 0, SQ_MU_FIXED = 1 } sq_mu_mode;
+
+/* One analytic species (the paper's pseudopotential data, Sec. V.A, is
+ * replaced by Gaussians): V(r) = -v_amp exp(-r^2 / (2 v_sigma^2)) for
+ * r < v_rcut; one s projector p(r) = exp(-r^2 / (2 p_sigma^2)) for
+ * r < p_rcut with energy gamma; z_val valence electrons. */
+typedef struct {
+  double v_amp, v_sigma, v_rcut;
+  double p_sigma, p_rcut, gamma;
+  double z_val;
+} sq_species;
+
+/* One periodic orthorhombic cell (Sec. II: sides L, nuclei R, N_e). */
+typedef struct {
+  double L[3];          /* cell sides; L[a] / h must be an integer (1e-9)   */
+  double h;             /* mesh size                                         */
+  int fd_half_order;    /* M: FD order 2M; 6 (12th order, Sec. V) supported */
+  int n_atoms;
+  const double* pos;    /* [n_atoms][3] positions, wrapped into [0, L)      */
+  const int* species;   /* [n_atoms] index into sp                          */
+  int n_species;
+  const sq_species* sp; /* [n_species]                                      */
+  double n_electrons;   /* N_e; < 0 means the sum of z_val                  */
+  double rcut;          /* truncation radius: cube of (2 floor(rcut/h)+1)^3 */
+  int npl;              /* Chebyshev degree n_pl (>= 1)                     */
+  double kT;            /* smearing sigma (Fermi-Dirac), Ha, > 0            */
+  int mu_mode;          /* sq_mu_mode                                       */
+  double mu;            /* Fermi level used when mu_mode == SQ_MU_FIXED      */
+  int lanczos_steps;    /* K of the spectral-bound Lanczos (>= 2; 0 -> 20)  */
+} sq_cell;
+
+typedef struct {
+  int precision;                                  /* sq_precision          */
+  void* hip_stream;                               /* hipStream_t or NULL   */
+  void* (*dev_alloc)(size_t bytes, void* ctx);    /* NULL: hipMalloc       */
+  void (*dev_free)(void* ptr, void* ctx);
+  void* alloc_ctx;
+  int outputs_on_device;   /* 1: output pointers below are device pointers */
+} sq_options;
+
+/* Validate the cells, build the per-cell tables (grid, atom images, local
+ * potential, per-tile image lists) and allocate the plan's device memory.
+ * Sec. IV: grid K_Omega, cube of side 2 R_cut, atoms of R^3 whose projectors
+ * meet the cube.  Returns SQ_E_ARG for a non-integral L/h, R_cut < h,
+ * npl outside [1, 256], kT <= 0, an FD order other than 12, or a cube
+ * narrower than 7 or wider than 25 nodes. */
+sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_plan* out);
+
+/* Spectral bounds, Chebyshev moments, Fermi level and density (Sec. IV).
+ * cell = -1 runs every cell of the plan in the same launches.
+ * rho: [N_d] per cell (concatenated in cell order), may be NULL;
+ * mu: one per cell, may be NULL.  SQ_E_BOUNDS if a moment left [-1, 1]
+ * (tolerance 1e-4), SQ_E_NOCONV if N_e is not bracketed. */
+sq_status sq_density(sq_plan plan, int cell, double* rho, double* mu);
+
+/* Band energy 2 sum_q sum'_j (chi_q c_q^j + zeta_q d_q^j) rho_q^j (App. A),
+ * one value per cell.  Needs sq_density first (SQ_E_STATE otherwise). */
+sq_status sq_energy(sq_plan plan, int cell, double* e_band);
+
+/* Kinetic + nonlocal density-matrix stress (Sec. IV) divided by |Omega|:
+ * sigma_voigt [6] per cell; parts [18] per cell (nullable): the node sums
+ * of K (3x3) then N (3x3), not divided by |Omega|.  Needs sq_density. */
+sq_status sq_stress(sq_plan plan, int cell, double* sigma_voigt, double* parts);
+
+/* Per-node records for a list of nodes of one cell: out [n][20] =
+ * rho_q, band-energy density e_q, K (9), N (9).  K and N need sq_stress
+ * first (zeros otherwise).  nodes are host arrays. */
+sq_status sq_nodes(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
+
+/* Per-node spectral bounds lambda_lo, lambda_hi ([N_d] each, host arrays),
+ * and moments rho_q^j for a list of nodes (out [n][npl+1]). */
+sq_status sq_bounds(sq_plan plan, int cell, double* lam_lo, double* lam_hi);
+sq_status sq_moments(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
+
+/* Lanczos tridiagonals behind the spectral bounds, for a list of nodes:
+ * out [n][2K+1] = steps taken, alpha_1..alpha_K, beta_1..beta_K (zeros past
+ * the steps taken), K = the cell's lanczos_steps.  Needs sq_density. */
+sq_status sq_lanczos(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
+
+/* Plan queries (info has 9 entries): info[0] = N_d, info[1] = n_c,
+ * info[2] = npl, info[3] = number of atom images, info[4] = max images in a
+ * node tile, info[5..7] = largest number of images reaching one cube,
+ * crossing one cube column, and nonzero at one node, info[8] = number of
+ * (node, projector) pairs over all nodes' cubes (measured at set-up). */
+sq_status sq_cell_info(sq_plan plan, int cell, int64_t* info);
+
+/* Device time of each phase accumulated over the calls since the last reset
+ * (HIP events on the plan's stream), ms [7] and call counts [7] in the
+ * order: Lanczos bounds, bound extraction, Chebyshev moments, Fermi level,
+ * coefficients + density, stress pass, final reductions.  reset != 0 zeroes
+ * the accumulators after reading.  Either output may be NULL. */
+sq_status sq_phase_times(sq_plan plan, int reset, double* ms, int64_t* count);
+
+const char* sq_status_str(sq_status s);
+/* Message of the last failed call on the plan; with plan == NULL, of the
+ * last failed sq_setup on the calling thread. */
+const char* sq_last_error(sq_plan plan);
+void sq_destroy(sq_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQ_H */

@@ -1,0 +1,97 @@
+// sq_dev.h -- device-side data layout shared by the host plan (sq_capi.cpp)
+// and the gfx950 kernels (sq_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SQ_FDM 6          // FD half order on the device (12th-order stencil)
+#define SQ_MAX_SPECIES 4
+#define SQ_NEAR_MAX 32    // images whose projector is nonzero at the node
+#define SQ_KL_MAX 64      // Lanczos steps
+#define SQ_REC 20         // per-node record: rho, e, K[9], N[9]
+#define SQ_TILE 2         // nodes per tile edge for the image lists
+
+// error bits raised by kernels
+#define SQ_ERR_SLOTS 1u
+#define SQ_ERR_IMAGES 2u
+#define SQ_ERR_BOUNDS 4u
+#define SQ_ERR_NEAR 8u
+
+struct SpecDev {
+  double v_amp, v_sig, v_rc, p_sig, p_rc, gamma;
+};
+
+// One cell as the kernels see it.  All per-node arrays are indexed by the
+// global node id g = node_base + q.
+struct CellDev {
+  int n[3];
+  int m, nc, npl, K;
+  int nimg;           // atom images of the cell (all that reach any cube)
+  int ntile[3];       // tiles per axis (SQ_TILE nodes per edge)
+  int nsp;
+  int pad0;
+  int mu_mode;
+  int pad1;
+  long long Nd, node_base;
+  double h, dV, kT, ne, vol, mu0;
+  double L[3];
+  double c2[SQ_FDM + 1], c1[SQ_FDM + 1];
+  SpecDev sp[SQ_MAX_SPECIES];
+  const double* vloc;     // [Nd]
+  const double* img;      // [nimg][4]: x, y, z (unwrapped), species
+  const int* tile_ptr;    // [ntiles + 1]
+  const int* tile_img;    // image ids per tile
+};
+
+// Device buffers of a plan (concatenated over cells).
+struct PlanDev {
+  const CellDev* cells;   // [ncell]
+  double* lan;            // [Ntot][2 * SQ_KL_MAX]  alpha then beta
+  int* lan_steps;         // [Ntot]
+  double* bnd;            // [Ntot][4]  lam_lo, lam_hi, chi, zeta
+  double* mom;            // [Ntot][mstride]
+  double* coef;           // [Ntot][mstride]
+  double* rec;            // [Ntot][SQ_REC]
+  double* nq;             // [Ntot]  per-node electron count at the trial mu
+  double* mus;            // [ncell][8] Fermi-level bisection state
+  double* sums;           // [ncell][SQ_REC + 4] reduced records
+  unsigned* err;          // [1]
+  int mstride;
+};
+
+// mus layout
+#define MU_LO 0
+#define MU_HI 1
+#define MU_MID 2
+#define MU_VAL 3
+#define MU_DONE 4
+#define MU_IT 5
+#define MU_PHASE 6
+#define MU_N 7
+
+extern "C++" {
+// launchers (sq_kernels.hip)
+hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s);
+hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
+                             const int* item_cell, long long nitems, hipStream_t s);
+hipError_t sq_launch_bounds(const PlanDev& P, const long long* items, const int* item_cell,
+                            long long nitems, hipStream_t s);
+hipError_t sq_launch_moments(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
+                             const int* item_cell, long long nitems, hipStream_t s);
+hipError_t sq_launch_mu_init(const PlanDev& P, const int* cells, int ncells, const int* fixed_mode,
+                             hipStream_t s);
+hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int* item_cell,
+                             long long nitems, hipStream_t s);
+hipError_t sq_launch_mu_step(const PlanDev& P, const int* cells, int ncells, hipStream_t s);
+hipError_t sq_launch_coeffs(const PlanDev& P, const long long* items, const int* item_cell,
+                            long long nitems, hipStream_t s);
+hipError_t sq_launch_stress(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
+                            const int* item_cell, long long nitems, hipStream_t s);
+hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
+                            long long nitems, int* stats, long long* pairs, hipStream_t s);
+int sq_kc_limit(bool fp64, int nc);
+hipError_t sq_launch_reduce(const PlanDev& P, const int* cells, int ncells, int col0, int ncol,
+                            hipStream_t s);
+bool sq_nc_supported(int nc);
+}

@@ -1,0 +1,1467 @@
+// sq_kernels.hip -- gfx950 kernels of the infinite-cell Clenshaw-Curtis SQ
+// hot path (arXiv 2006.03697, Sec. IV and App. A).
+//
+// One workgroup owns one node q and its cube (region of influence) of
+// NC^3 finite-difference nodes.  Thread (cx, cy) owns the z-column of the
+// cube at (cx, cy): the current Chebyshev vector, the previous one and the
+// diagonal of H_q on that column live in its registers; the current vector
+// is mirrored in LDS so that x/y neighbours of the 12th-order stencil are
+// LDS reads and z neighbours are register reads.  Atom-image projectors are
+// evaluated from separable Gaussian factors: per image a table of the
+// z factor (LDS) and, per (column, image), the xy factor and the z chord of
+// the spherical support (registers, computed once per node).
+#include "sq_dev.h"
+
+#include <math.h>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// geometry helpers: the same IEEE operations as the oracle, no contraction
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double node_coord(long long i, double h, double R) {
+#pragma clang fp contract(off)
+  return (double)i * h - R;
+}
+
+__device__ __forceinline__ double sq_sum2(double a, double b) {
+#pragma clang fp contract(off)
+  return a * a + b * b;
+}
+
+__device__ __forceinline__ double sq_add(double s, double c) {
+#pragma clang fp contract(off)
+  return s + c * c;
+}
+
+__device__ __forceinline__ long long wrapll(long long i, long long n) {
+  long long r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// Make a register value opaque to the optimiser (no hoisting of values
+// derived from it); 64-bit values go through their two 32-bit halves.
+#ifdef SQ_NO_OPAQUE
+template <typename U>
+__device__ __forceinline__ void opaque(U&) {}
+#else
+__device__ __forceinline__ void opaque(int& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(float& x) {
+  unsigned u = __float_as_uint(x);
+  asm volatile("" : "+v"(u));
+  x = __uint_as_float(u);
+}
+__device__ __forceinline__ void opaque(double& x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  asm volatile("" : "+v"(lo), "+v"(hi));
+  x = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+#endif
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Fixed-order block sum of two values (deterministic); red has 2*NW slots.
+template <int NW>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  a = warp_sum(a);
+  b = warp_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+    red[w] = a;
+    red[NW + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    sa += red[i];
+    sb += red[NW + i];
+  }
+  __syncthreads();
+  a = sa;
+  b = sb;
+}
+
+__device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
+  double t = ceil(8.0 * zeta / kT);
+  double tgt = fmax((double)(4 * (npl + 2)), t);
+  int M = 1;
+  while ((double)M < tgt) M <<= 1;
+  return M;
+}
+
+template <int NC>
+struct Geo {
+  static constexpr int NC2 = NC * NC;
+  static constexpr int NC3 = NC2 * NC;
+  static constexpr int NT = ((NC2 + 63) / 64) * 64;
+  static constexpr int NW = NT / 64;
+  static constexpr int MH = NC / 2;
+};
+
+// A kernel variant: working precision T, cube width NC, KC image slots per
+// z-column, and where the xy factor of a projector on a column comes from
+// (SEP: product of two per-image tables in LDS; otherwise a register per
+// slot).  The LDS layout of the cube vector is padded with zero halos when
+// the whole working set still fits the 160 KiB of LDS.
+template <typename T_, int NC_, int KC_, bool SEP_>
+struct Var {
+  using T = T_;
+  static constexpr int NC = NC_;
+  static constexpr int KC = KC_;
+  static constexpr bool SEP = SEP_;
+  static constexpr int NIMG = sizeof(T_) == 4 ? 160 : 112;
+  static constexpr int NEAR = 32;
+  static constexpr int PRS = NC_ + SQ_FDM;
+  static constexpr int PPL = (NC_ + SQ_FDM) * PRS;
+  static constexpr size_t OTHER = sizeof(T_) * (size_t)NIMG * NC_ * (SEP_ ? 3 : 1) +
+                                  8 * (size_t)NIMG * 8 + (size_t)NEAR * 11 * 8 + NEAR * 4 + 1024;
+  static constexpr size_t PADDED = sizeof(T_) * (size_t)(SQ_FDM * PRS + SQ_FDM + NC_ * PPL);
+#ifdef SQ_NO_PAD
+  static constexpr bool PAD = false;
+#else
+  static constexpr bool PAD = PADDED + OTHER <= 163840;
+#endif
+};
+
+// LDS layout of one cube vector.  Padded: every row is followed by SQ_FDM
+// zero columns and every plane by SQ_FDM zero rows, and the array starts
+// with SQ_FDM zero rows plus SQ_FDM zeros, so x and y neighbours outside the
+// cube read zeros and need no predicate.
+template <class Vr>
+struct Lay {
+  static constexpr int NC = Vr::NC;
+  static constexpr bool PAD = Vr::PAD;
+  static constexpr int RS = PAD ? Vr::PRS : NC;                    // row stride
+  static constexpr int PL = PAD ? Vr::PPL : NC * NC;               // plane stride
+  static constexpr int X0 = PAD ? SQ_FDM * Vr::PRS + SQ_FDM : 0;   // offset of (0,0,0)
+  static constexpr int SIZE = X0 + NC * PL;
+  __device__ static constexpr int at(int x, int y, int z) { return X0 + z * PL + y * RS + x; }
+};
+
+template <class Vr>
+struct Smem {
+  using T = typename Vr::T;
+  static constexpr int NI = Vr::NIMG;
+  T tl[Lay<Vr>::SIZE];
+  T ez[NI][Vr::NC];
+  T ex[Vr::SEP ? NI : 1][Vr::NC];
+  T ey[Vr::SEP ? NI : 1][Vr::NC];
+  double ix[NI], iy[NI], iz[NI];
+  double rp2[NI], i2s[NI], gdv[NI];
+  double pacc[2][NI];
+  double red[2 * 16];
+  double near_chi[Vr::NEAR];
+  double nsum[Vr::NEAR][10];
+  int near_img[Vr::NEAR];
+  int wcnt[16];
+  int nimg, nnear;
+};
+
+// Per-thread node context (registers).
+template <class Vr>
+struct Ctx {
+  using T = typename Vr::T;
+  int cx, cy, col;
+  bool active;
+  long long q0, q1, q2;
+  int nslot;
+  int sid[Vr::KC];                  // image | z0 << 8 | z1 << 16
+  T sexy[Vr::SEP ? 1 : Vr::KC];     // xy factor of the projector (register variant)
+  T vd[Vr::NC];                     // diagonal of (H_q - shift) without the stencil centre
+};
+
+template <class Vr>
+__device__ __forceinline__ typename Vr::T slot_exy(const Smem<Vr>& S, const Ctx<Vr>& X, int s, int i) {
+  if constexpr (Vr::SEP)
+    return S.ex[i][X.cx] * S.ey[i][X.cy];
+  else
+    return X.sexy[s];
+}
+
+// Image list of the node's cube: the tile list filtered by distance to the
+// cube's box, in tile-list order (deterministic).  Returns the count.
+template <int NT, int NW, int CAP, class Store>
+__device__ __forceinline__ int gather_images(const CellDev& C, long long q0, long long q1,
+                                             long long q2, int m, int* cnt_lds, int* wcnt,
+                                             Store store, unsigned* err) {
+  const int tid = threadIdx.x;
+  const double h = C.h;
+  const int tx = (int)(q0 / SQ_TILE), ty = (int)(q1 / SQ_TILE), tz = (int)(q2 / SQ_TILE);
+  const int tile = tx + C.ntile[0] * (ty + C.ntile[1] * tz);
+  const int t0 = C.tile_ptr[tile], t1 = C.tile_ptr[tile + 1];
+  if (tid == 0) *cnt_lds = 0;
+  __syncthreads();
+  const double lo0 = (double)(q0 - m) * h, hi0 = (double)(q0 + m) * h;
+  const double lo1 = (double)(q1 - m) * h, hi1 = (double)(q1 + m) * h;
+  const double lo2 = (double)(q2 - m) * h, hi2 = (double)(q2 + m) * h;
+  int total = 0;
+  for (int base = t0; base < t1; base += NT) {
+    const int k = base + tid;
+    bool pass = false;
+    int I = 0;
+    if (k < t1) {
+      I = C.tile_img[k];
+      const double R0 = C.img[4 * I], R1 = C.img[4 * I + 1], R2 = C.img[4 * I + 2];
+      const int sp = (int)C.img[4 * I + 3];
+      const double e0 = R0 < lo0 ? lo0 - R0 : (R0 > hi0 ? R0 - hi0 : 0.0);
+      const double e1 = R1 < lo1 ? lo1 - R1 : (R1 > hi1 ? R1 - hi1 : 0.0);
+      const double e2 = R2 < lo2 ? lo2 - R2 : (R2 > hi2 ? R2 - hi2 : 0.0);
+      const double rp = C.sp[sp].p_rc;
+      // conservative: an image that is kept but reaches no node adds zero
+      pass = e0 * e0 + e1 * e1 + e2 * e2 < rp * rp * (1.0 + 1e-9) + 1e-12;
+    }
+    const unsigned long long mask = __ballot(pass);
+    const int lane = tid & 63, w = tid >> 6;
+    const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[w] = __popcll(mask);
+    __syncthreads();
+    int off = *cnt_lds;
+    int chunk = 0;
+    for (int i = 0; i < NW; ++i) {
+      if (i < w) off += wcnt[i];
+      chunk += wcnt[i];
+    }
+    if (pass) {
+      const int pos = off + pre;
+      if (pos < CAP) store(pos, I);
+      else atomicOr(err, SQ_ERR_IMAGES);
+    }
+    __syncthreads();
+    if (tid == 0) *cnt_lds += chunk;
+    total += chunk;
+    __syncthreads();
+  }
+  return total;   // may exceed CAP (then only CAP were stored and err is set)
+}
+
+// Node prologue: image list of the cube, projector factor tables, per-column
+// chords, diagonal.  shift is subtracted from the diagonal.
+template <class Vr>
+__device__ __forceinline__ void node_prologue(const CellDev& C, long long q, double shift,
+                                              Smem<Vr>& S, Ctx<Vr>& X, unsigned* err) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  using G = Geo<NC>;
+  const int m = G::MH;
+  const int tid = threadIdx.x;
+  X.cx = tid % NC;
+  X.cy = tid / NC;
+  X.active = tid < G::NC2;
+  X.col = X.cx + NC * X.cy;
+  X.q0 = q % C.n[0];
+  X.q1 = (q / C.n[0]) % C.n[1];
+  X.q2 = q / ((long long)C.n[0] * C.n[1]);
+  const double h = C.h;
+
+  // ---- images whose projector may reach this cube ----
+  auto store = [&](int pos, int I) {
+    const SpecDev& s = C.sp[(int)C.img[4 * I + 3]];
+    S.ix[pos] = C.img[4 * I];
+    S.iy[pos] = C.img[4 * I + 1];
+    S.iz[pos] = C.img[4 * I + 2];
+    S.rp2[pos] = s.p_rc * s.p_rc;
+    S.i2s[pos] = 1.0 / (2.0 * s.p_sig * s.p_sig);
+    S.gdv[pos] = s.gamma * C.dV;
+  };
+  const int found = gather_images<G::NT, G::NW, Vr::NIMG>(C, X.q0, X.q1, X.q2, m, &S.nimg,
+                                                           S.wcnt, store, err);
+  const int nimg = found < Vr::NIMG ? found : Vr::NIMG;
+  if (tid == 0) S.nimg = nimg;
+
+  // ---- separable factors of every image on the cube's planes / columns ----
+  for (int idx = tid; idx < nimg * NC; idx += G::NT) {
+    const int i = idx / NC, z = idx % NC;
+    const double dz = node_coord(X.q2 + z - m, h, S.iz[i]);
+    S.ez[i][z] = (T)exp(-(dz * dz) * S.i2s[i]);
+    if constexpr (Vr::SEP) {
+      const double dx = node_coord(X.q0 + z - m, h, S.ix[i]);
+      const double dy = node_coord(X.q1 + z - m, h, S.iy[i]);
+      S.ex[i][z] = (T)exp(-(dx * dx) * S.i2s[i]);
+      S.ey[i][z] = (T)exp(-(dy * dy) * S.i2s[i]);
+    }
+  }
+  for (int i = tid; i < Vr::NIMG; i += G::NT) {
+    S.pacc[0][i] = 0.0;
+    S.pacc[1][i] = 0.0;
+  }
+  for (int i = tid; i < Lay<Vr>::SIZE; i += G::NT) S.tl[i] = (T)0;
+  if (tid == 0) S.nnear = 0;
+
+  // ---- per-column chords of every image's spherical support ----
+  X.nslot = 0;
+#pragma unroll
+  for (int s = 0; s < Vr::KC; ++s) X.sid[s] = 0;
+  if constexpr (!Vr::SEP) {
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) X.sexy[s] = (T)0;
+  }
+  if (X.active) {
+    for (int i = 0; i < nimg; ++i) {
+      const double dx = node_coord(X.q0 + X.cx - m, h, S.ix[i]);
+      const double dy = node_coord(X.q1 + X.cy - m, h, S.iy[i]);
+      const double dxy2 = sq_sum2(dx, dy);
+      const double rp2 = S.rp2[i];
+      if (!(dxy2 < rp2)) continue;
+      int z0 = -1, z1 = -2;
+      for (int z = 0; z < NC; ++z) {
+        const double dz = node_coord(X.q2 + z - m, h, S.iz[i]);
+        if (sq_add(dxy2, dz) < rp2) {
+          if (z0 < 0) z0 = z;
+          z1 = z;
+        }
+      }
+      if (z0 < 0) continue;
+      if (X.nslot >= Vr::KC) {
+        atomicOr(err, SQ_ERR_SLOTS);
+        continue;
+      }
+      const int packed = i | (z0 << 8) | (z1 << 16);
+      T exy = (T)0;
+      if constexpr (!Vr::SEP) exy = (T)exp(-dxy2 * S.i2s[i]);
+#pragma unroll
+      for (int s = 0; s < Vr::KC; ++s)
+        if (s == X.nslot) {
+          X.sid[s] = packed;
+          if constexpr (!Vr::SEP) X.sexy[s] = exy;
+        }
+      ++X.nslot;
+    }
+  }
+
+  // ---- diagonal: local potential (periodic) + stencil centre - shift ----
+  const double cdiag = -0.5 / (h * h) * 3.0 * C.c2[0];
+  const long long ix = wrapll(X.q0 + X.cx - m, C.n[0]);
+  const long long iy = wrapll(X.q1 + X.cy - m, C.n[1]);
+#pragma unroll
+  for (int z = 0; z < NC; ++z) {
+    double v = 0.0;
+    if (X.active) {
+      const long long iz = wrapll(X.q2 + z - m, C.n[2]);
+      v = C.vloc[ix + (long long)C.n[0] * (iy + (long long)C.n[1] * iz)];
+    }
+    X.vd[z] = (T)(v + cdiag - shift);
+  }
+  __syncthreads();
+}
+
+// One application of the nodal operator to the vector held in S.tl / cur:
+//   io <- sc * ((H_q - shift) cur) - pm * io
+// (io holds the previous vector on entry and the new one on exit, mirrored
+// in S.tl).  par selects the projection accumulator (alternates per call).
+template <class Vr>
+__device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X,
+                                           const typename Vr::T (&cur)[Vr::NC],
+                                           typename Vr::T (&io)[Vr::NC], const typename Vr::T* ck,
+                                           double sc, typename Vr::T pm, int par) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  using G = Geo<NC>;
+  using Ly = Lay<Vr>;
+  const int nimg = S.nimg;
+  // keep the per-node slot data opaque so that nothing derived from it is
+  // hoisted across steps (register pressure)
+#pragma unroll
+  for (int s = 0; s < Vr::KC; ++s) opaque(X.sid[s]);
+  if constexpr (!Vr::SEP) {
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) opaque(X.sexy[s]);
+  }
+  const int base = Ly::at(X.cx, X.cy, 0);
+  // (1) projections <chi_I, cur> of every image
+  if (X.active) {
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) {
+      if (s < X.nslot) {
+        const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
+        T part = (T)0;
+        for (int z = z0; z <= z1; ++z) part += S.ez[i][z] * S.tl[base + z * Ly::PL];
+        atomicAdd(&S.pacc[par][i], (double)(slot_exy<Vr>(S, X, s, i) * part));
+      }
+    }
+  }
+  __syncthreads();
+  // (2) stencil + diagonal on the own column (x/y neighbours from LDS)
+  if (X.active) {
+    const int cx = X.cx, cy = X.cy;
+    const T tsc = (T)sc;
+#pragma unroll
+    for (int z = 0; z < NC; ++z) {
+      T acc = X.vd[z] * cur[z];
+      const T* pc = S.tl + base + z * Ly::PL;
+#pragma unroll
+      for (int k = 1; k <= SQ_FDM; ++k) {
+        T s = (T)0;
+        if (z + k < NC) s += cur[z + k];
+        if (z - k >= 0) s += cur[z - k];
+        if constexpr (Ly::PAD) {
+          s += (pc[k] + pc[-k]) + (pc[k * Ly::RS] + pc[-k * Ly::RS]);
+        } else {
+          if (cx + k < NC) s += pc[k];
+          if (cx - k >= 0) s += pc[-k];
+          if (cy + k < NC) s += pc[k * Ly::RS];
+          if (cy - k >= 0) s += pc[-k * Ly::RS];
+        }
+        acc += ck[k] * s;
+      }
+      io[z] = tsc * acc - pm * io[z];
+    }
+  }
+  for (int i = threadIdx.x; i < nimg; i += G::NT) S.pacc[par ^ 1][i] = 0.0;
+  __syncthreads();
+  // (3) the projector terms, added through the LDS copy of the own column
+  if (X.active) {
+#pragma unroll
+    for (int z = 0; z < NC; ++z) S.tl[base + z * Ly::PL] = io[z];
+    if (X.nslot > 0) {
+#pragma unroll
+      for (int s = 0; s < Vr::KC; ++s) {
+        if (s < X.nslot) {
+          const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
+          const T coef = (T)(sc * S.gdv[i] * S.pacc[par][i]) * slot_exy<Vr>(S, X, s, i);
+          for (int z = z0; z <= z1; ++z) S.tl[base + z * Ly::PL] += coef * S.ez[i][z];
+        }
+      }
+#pragma unroll
+      for (int z = 0; z < NC; ++z) io[z] = S.tl[base + z * Ly::PL];
+    }
+  }
+  __syncthreads();
+}
+
+template <class Vr>
+__device__ __forceinline__ void load_unit(Smem<Vr>& S, Ctx<Vr>& X, typename Vr::T (&cur)[Vr::NC],
+                                          typename Vr::T (&prv)[Vr::NC]) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  using G = Geo<NC>;
+#pragma unroll
+  for (int z = 0; z < NC; ++z) {
+    cur[z] = (X.cx == G::MH && X.cy == G::MH && z == G::MH) ? (T)1 : (T)0;
+    prv[z] = (T)0;
+    if (X.active) S.tl[Lay<Vr>::at(X.cx, X.cy, z)] = cur[z];
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void stencil_coefs(const CellDev& C, T* ck) {
+  const double s = -0.5 / (C.h * C.h);
+  ck[0] = (T)0;
+#pragma unroll
+  for (int k = 1; k <= SQ_FDM; ++k) ck[k] = (T)(s * C.c2[k]);
+}
+
+// ---------------------------------------------------------------------------
+// Spectral bounds: K-step FP64 Lanczos on H_q from the unit vector w_q
+// (chi_q and zeta_q come from the extreme eigenvalues of H_q, Sec. IV)
+// ---------------------------------------------------------------------------
+// One Lanczos step with v_k in A (and S.tl), v_{k-1} in B on entry; on exit
+// v_{k+1} is in B (and S.tl) unless the recursion stopped.
+template <class Vr>
+__device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const double (&A)[Vr::NC],
+                                             double (&B)[Vr::NC], const double* ck, int k,
+                                             double& bprev, double& tol, double* lan) {
+  constexpr int NC = Vr::NC;
+  using G = Geo<NC>;
+  apply_step<Vr>(S, X, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
+  double a = 0.0, dum = 0.0;
+#pragma unroll
+  for (int z = 0; z < NC; ++z) a += A[z] * B[z];
+  block_sum2<G::NW>(a, dum, S.red);
+  double b = 0.0;
+#pragma unroll
+  for (int z = 0; z < NC; ++z) {
+    B[z] -= a * A[z];
+    b += B[z] * B[z];
+  }
+  block_sum2<G::NW>(b, dum, S.red);
+  b = sqrt(b);
+  if (threadIdx.x == 0) {
+    lan[k] = a;
+    lan[SQ_KL_MAX + k] = b;
+  }
+  if (k == 0) tol = 1e-14 * (fabs(a) + b);
+  if (b < tol) return false;
+  const double ib = 1.0 / b;
+#pragma unroll
+  for (int z = 0; z < NC; ++z) {
+    B[z] *= ib;
+    if (X.active) S.tl[Lay<Vr>::at(X.cx, X.cy, z)] = B[z];
+  }
+  bprev = b;
+  __syncthreads();
+  return true;
+}
+
+template <class Vr>
+__global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_lanczos(PlanDev P, const long long* items,
+                                                              const int* item_cell) {
+  static_assert(sizeof(typename Vr::T) == 8, "Lanczos runs in FP64");
+  constexpr int NC = Vr::NC;
+  __shared__ Smem<Vr> S;
+  const long long g = items[blockIdx.x];
+  const CellDev& C = P.cells[item_cell[blockIdx.x]];
+  const long long q = g - C.node_base;
+  Ctx<Vr> X;
+  node_prologue<Vr>(C, q, 0.0, S, X, P.err);
+  double ck[SQ_FDM + 1];
+  stencil_coefs<double>(C, ck);
+  double A[NC], B[NC];
+  load_unit<Vr>(S, X, A, B);
+  double bprev = 0.0, tol = 0.0;
+  int steps = 0;
+  double* lan = P.lan + g * (2 * SQ_KL_MAX);
+  for (int k = 0; k < C.K; k += 2) {
+    steps = k + 1;
+    if (!lanczos_step<Vr>(S, X, A, B, ck, k, bprev, tol, lan)) break;
+    if (k + 1 >= C.K) break;
+    steps = k + 2;
+    if (!lanczos_step<Vr>(S, X, B, A, ck, k + 1, bprev, tol, lan)) break;
+  }
+  if (threadIdx.x == 0) P.lan_steps[g] = steps;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev moments rho_q^j = w_q^T T_j(Hhat_q) w_q, j = 0..npl, from the
+// three-term recurrence (Sec. IV) taken to degree ceil(npl/2) with
+//   rho^{2k} = 2 <t^k, t^k> - rho^0,  rho^{2k+1} = 2 <t^{k+1}, t^k> - rho^1
+// (Hhat_q is symmetric, T_{a+b} + T_{|a-b|} = 2 T_a T_b).
+// ---------------------------------------------------------------------------
+template <class Vr>
+__global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_moments(PlanDev P, const long long* items,
+                                                              const int* item_cell) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  using G = Geo<NC>;
+  __shared__ Smem<Vr> S;
+  const long long g = items[blockIdx.x];
+  const CellDev& C = P.cells[item_cell[blockIdx.x]];
+  const long long q = g - C.node_base;
+  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+  Ctx<Vr> X;
+  node_prologue<Vr>(C, q, chi, S, X, P.err);
+  T ck[SQ_FDM + 1];
+  stencil_coefs<T>(C, ck);
+  T A[NC], B[NC];
+  load_unit<Vr>(S, X, A, B);
+  double* mom = P.mom + g * P.mstride;
+  const int npl = C.npl;
+  const int kmax = (npl + 1) / 2;
+  double rho1 = 0.0;
+  bool bad = false;
+  if (threadIdx.x == 0) mom[0] = 1.0;
+  // t^{k+1} from t^k (cur) and t^{k-1} (io); then rho^{2k+1}, rho^{2k+2}
+  auto step = [&](const T (&cur)[NC], T (&io)[NC], int k) {
+    apply_step<Vr>(S, X, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, k == 0 ? (T)0 : (T)1,
+                   k & 1);
+    double sq = 0.0, cr = 0.0;
+#pragma unroll
+    for (int z = 0; z < NC; ++z) {
+      const double a = (double)io[z], b = (double)cur[z];
+      sq += a * a;
+      cr += a * b;
+    }
+    block_sum2<G::NW>(sq, cr, S.red);
+    if (k == 0) rho1 = cr;
+    const int j1 = 2 * k + 1, j2 = 2 * k + 2;
+    const double r1 = (k == 0) ? cr : 2.0 * cr - rho1;
+    const double r2 = 2.0 * sq - 1.0;
+    if (fabs(r1) > 1.0 + 1e-4 || (j2 <= npl && fabs(r2) > 1.0 + 1e-4) || !(r1 == r1)) bad = true;
+    if (threadIdx.x == 0) {
+      mom[j1] = r1;
+      if (j2 <= npl) mom[j2] = r2;
+    }
+  };
+  for (int k = 0; k < kmax; k += 2) {
+    step(A, B, k);
+    if (k + 1 < kmax) step(B, A, k + 1);
+  }
+  if (bad && threadIdx.x == 0) atomicOr(P.err, SQ_ERR_BOUNDS);
+}
+
+// ---------------------------------------------------------------------------
+// Stress pass: recurrence again with the coefficients known, the DM column
+// d_q = sum'_j c_q^j t^j accumulated in FP64, then the kinetic functional
+// K_ab = 2 (grad_a grad_b d_q)_q and the nonlocal functional
+// N_ab = -2 sum_I gamma dV chi_I(x_q) [delta_ab chi_I^T d_q
+//        + 2 sum_y chi_I(y) (y_b - R_Ib) (grad_a d_q)(y)]   (Sec. IV)
+// ---------------------------------------------------------------------------
+template <class Vr>
+__device__ __forceinline__ void grad_xy_round(Smem<Vr>& S, Ctx<Vr>& X,
+                                              const typename Vr::T (&part)[Vr::NC],
+                                              double (&gx)[Vr::NC], double (&gy)[Vr::NC],
+                                              const double* w) {
+  constexpr int NC = Vr::NC;
+  using T = typename Vr::T;
+  using Ly = Lay<Vr>;
+  const int base = Ly::at(X.cx, X.cy, 0);
+  if (X.active) {
+#pragma unroll
+    for (int z = 0; z < NC; ++z) S.tl[base + z * Ly::PL] = part[z];
+  }
+  __syncthreads();
+  if (X.active) {
+    const int cx = X.cx, cy = X.cy;
+#pragma unroll
+    for (int z = 0; z < NC; ++z) {
+      const T* pc = S.tl + base + z * Ly::PL;
+      double ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int k = 1; k <= SQ_FDM; ++k) {
+        if constexpr (Ly::PAD) {
+          ax += w[k] * ((double)pc[k] - (double)pc[-k]);
+          ay += w[k] * ((double)pc[k * Ly::RS] - (double)pc[-k * Ly::RS]);
+        } else {
+          if (cx + k < NC) ax += w[k] * (double)pc[k];
+          if (cx - k >= 0) ax -= w[k] * (double)pc[-k];
+          if (cy + k < NC) ay += w[k] * (double)pc[k * Ly::RS];
+          if (cy - k >= 0) ay -= w[k] * (double)pc[-k * Ly::RS];
+        }
+      }
+      gx[z] += ax;
+      gy[z] += ay;
+    }
+  }
+  __syncthreads();
+}
+
+template <class Vr>
+__global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const long long* items,
+                                                             const int* item_cell) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  using G = Geo<NC>;
+  constexpr int m = G::MH;
+  __shared__ Smem<Vr> S;
+  const long long g = items[blockIdx.x];
+  const CellDev& C = P.cells[item_cell[blockIdx.x]];
+  const long long q = g - C.node_base;
+  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+  const double* coef = P.coef + g * P.mstride;
+  Ctx<Vr> X;
+  node_prologue<Vr>(C, q, chi, S, X, P.err);
+  T ck[SQ_FDM + 1];
+  stencil_coefs<T>(C, ck);
+  T A[NC], B[NC];
+  load_unit<Vr>(S, X, A, B);
+  double d[NC];
+  const double c0h = 0.5 * coef[0];
+#pragma unroll
+  for (int z = 0; z < NC; ++z) d[z] = c0h * (double)A[z];
+  const int npl = C.npl;
+  auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
+    apply_step<Vr>(S, X, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta, j == 0 ? (T)0 : (T)1,
+                   j & 1);
+    const double cj = coef[j + 1];
+#pragma unroll
+    for (int z = 0; z < NC; ++z) d[z] += cj * (double)io[z];
+  };
+  for (int j = 0; j < npl; j += 2) {
+    step(A, B, j);
+    if (j + 1 < npl) step(B, A, j + 1);
+  }
+
+  // ---- gradients of d along x, y (LDS, FP64 via hi/lo rounds) and z ----
+  const double ih = 1.0 / C.h;
+  double w[SQ_FDM + 1];
+#pragma unroll
+  for (int k = 0; k <= SQ_FDM; ++k) w[k] = C.c1[k];
+  double gx[NC], gy[NC], gz[NC];
+#pragma unroll
+  for (int z = 0; z < NC; ++z) {
+    gx[z] = 0.0;
+    gy[z] = 0.0;
+    double a = 0.0;
+#pragma unroll
+    for (int k = 1; k <= SQ_FDM; ++k) {
+      if (z + k < NC) a += w[k] * d[z + k];
+      if (z - k >= 0) a -= w[k] * d[z - k];
+    }
+    gz[z] = a * ih;
+  }
+  {
+    T hi[NC];
+#pragma unroll
+    for (int z = 0; z < NC; ++z) hi[z] = (T)d[z];
+    grad_xy_round<Vr>(S, X, hi, gx, gy, w);
+    if constexpr (sizeof(T) < sizeof(double)) {
+#pragma unroll
+      for (int z = 0; z < NC; ++z) hi[z] = (T)(d[z] - (double)hi[z]);
+      grad_xy_round<Vr>(S, X, hi, gx, gy, w);
+    }
+#pragma unroll
+    for (int z = 0; z < NC; ++z) {
+      gx[z] *= ih;
+      gy[z] *= ih;
+    }
+  }
+
+  // ---- kinetic functional from the plane z = m and the centre column ----
+  double* plane = reinterpret_cast<double*>(S.tl);   // 3 * NC2 + 3 * NC doubles
+  static_assert(sizeof(T) * Lay<Vr>::SIZE >= sizeof(double) * (3 * G::NC2 + 3 * NC), "plane");
+  if (X.active) {
+    plane[X.col] = gx[m];
+    plane[G::NC2 + X.col] = gy[m];
+    plane[2 * G::NC2 + X.col] = gz[m];
+    if (X.cx == m && X.cy == m) {
+#pragma unroll
+      for (int z = 0; z < NC; ++z) {
+        plane[3 * G::NC2 + z] = gx[z];
+        plane[3 * G::NC2 + NC + z] = gy[z];
+        plane[3 * G::NC2 + 2 * NC + z] = gz[z];
+      }
+    }
+  }
+  // ---- near images: projector nonzero at the node itself ----
+  if (X.active && X.cx == m && X.cy == m) {
+    int nn = 0;
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) {
+      if (s < X.nslot) {
+        const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
+        if (z0 <= m && m <= z1) {
+          if (nn < Vr::NEAR) {
+            S.near_img[nn] = i;
+            const double dx = node_coord(X.q0, C.h, S.ix[i]);
+            const double dy = node_coord(X.q1, C.h, S.iy[i]);
+            const double dz = node_coord(X.q2, C.h, S.iz[i]);
+            S.near_chi[nn] = exp(-sq_add(sq_sum2(dx, dy), dz) * S.i2s[i]);
+          } else {
+            atomicOr(P.err, SQ_ERR_NEAR);
+          }
+          ++nn;
+        }
+      }
+    }
+    S.nnear = nn < Vr::NEAR ? nn : Vr::NEAR;
+  }
+  for (int i = threadIdx.x; i < Vr::NEAR * 10; i += G::NT) (&S.nsum[0][0])[i] = 0.0;
+  __syncthreads();
+
+  double* rec = P.rec + g * SQ_REC;
+  if (threadIdx.x == 0) {
+    const double* px = plane;
+    const double* py = plane + G::NC2;
+    const double* pz = plane + 2 * G::NC2;
+    const double* cxg = plane + 3 * G::NC2;
+    // (grad_a G_b)(c) = (1/h) sum_k w_k (G_b(c + k e_a) - G_b(c - k e_a))
+    for (int b = 0; b < 3; ++b) {
+      const double* pb = b == 0 ? px : (b == 1 ? py : pz);
+      const double* cb = cxg + b * NC;
+      double kx = 0.0, ky = 0.0, kz = 0.0;
+      for (int k = 1; k <= SQ_FDM; ++k) {
+        if (k > m) break;
+        kx += w[k] * (pb[m * NC + m + k] - pb[m * NC + m - k]);
+        ky += w[k] * (pb[(m + k) * NC + m] - pb[(m - k) * NC + m]);
+        kz += w[k] * (cb[m + k] - cb[m - k]);
+      }
+      rec[2 + 0 * 3 + b] = 2.0 * kx * ih;
+      rec[2 + 1 * 3 + b] = 2.0 * ky * ih;
+      rec[2 + 2 * 3 + b] = 2.0 * kz * ih;
+    }
+  }
+
+  // ---- nonlocal sums over the support of every near image ----
+  const int nnear = S.nnear;
+  if (X.active && nnear > 0) {
+    const double xc = (double)(X.q0 + X.cx - m) * C.h;
+    const double yc = (double)(X.q1 + X.cy - m) * C.h;
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) {
+      if (s < X.nslot) {
+        const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
+        int nidx = -1;
+        for (int n = 0; n < nnear; ++n)
+          if (S.near_img[n] == i) nidx = n;
+        if (nidx >= 0) {
+          const double exy = (double)slot_exy<Vr>(S, X, s, i);
+          const double rx = xc - S.ix[i], ry = yc - S.iy[i];
+          double acc[10];
+#pragma unroll
+          for (int t = 0; t < 10; ++t) acc[t] = 0.0;
+#pragma unroll
+          for (int z = 0; z < NC; ++z) {
+            if (z >= z0 && z <= z1) {
+              const double chiv = exy * (double)S.ez[i][z];
+              const double rz = (double)(X.q2 + z - m) * C.h - S.iz[i];
+              acc[0] += chiv * d[z];
+              const double ga[3] = {gx[z], gy[z], gz[z]};
+              const double rb[3] = {rx, ry, rz};
+#pragma unroll
+              for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += chiv * rb[b] * ga[a];
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < 10; ++t) atomicAdd(&S.nsum[nidx][t], acc[t]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double N[9];
+    for (int t = 0; t < 9; ++t) N[t] = 0.0;
+    for (int n = 0; n < nnear; ++n) {
+      const int i = S.near_img[n];
+      const double f = -2.0 * S.gdv[i] * S.near_chi[n];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+          N[3 * a + b] += f * ((a == b ? S.nsum[n][0] : 0.0) + 2.0 * S.nsum[n][1 + 3 * a + b]);
+    }
+    for (int t = 0; t < 9; ++t) rec[11 + t] = N[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Capacity census (set-up time): per node the number of atom images reaching
+// its cube, the largest number crossing one z-column, and the number whose
+// projector is nonzero at the node.  Maxima per cell go to stats[3 * cell].
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ void __launch_bounds__(Geo<NC>::NT) k_census(PlanDev P, const long long* items,
+                                                         const int* item_cell, int* stats,
+                                                         long long* pair_total) {
+  using G = Geo<NC>;
+  constexpr int CAP = 512;
+  __shared__ double sx[CAP], sy[CAP], sz[CAP], srp2[CAP];
+  __shared__ int wcnt[16], cnt, colmax, nnear;
+  __shared__ unsigned long long npairs;
+  const long long g = items[blockIdx.x];
+  const int ci = item_cell[blockIdx.x];
+  const CellDev& C = P.cells[ci];
+  const long long q = g - C.node_base;
+  const int m = G::MH;
+  const long long q0 = q % C.n[0], q1 = (q / C.n[0]) % C.n[1], q2 = q / ((long long)C.n[0] * C.n[1]);
+  auto store = [&](int pos, int I) {
+    sx[pos] = C.img[4 * I];
+    sy[pos] = C.img[4 * I + 1];
+    sz[pos] = C.img[4 * I + 2];
+    const double rp = C.sp[(int)C.img[4 * I + 3]].p_rc;
+    srp2[pos] = rp * rp;
+  };
+  const int found = gather_images<G::NT, G::NW, CAP>(C, q0, q1, q2, m, &cnt, wcnt, store, P.err);
+  const int nimg = found < CAP ? found : CAP;
+  if (threadIdx.x == 0) {
+    colmax = 0;
+    nnear = 0;
+    npairs = 0;
+  }
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < G::NC2) {
+    const int cx = tid % NC, cy = tid / NC;
+    int count = 0, near = 0, pairs = 0;
+    for (int i = 0; i < nimg; ++i) {
+      const double dx = node_coord(q0 + cx - m, C.h, sx[i]);
+      const double dy = node_coord(q1 + cy - m, C.h, sy[i]);
+      const double dxy2 = sq_sum2(dx, dy);
+      if (!(dxy2 < srp2[i])) continue;
+      bool any = false;
+      for (int z = 0; z < NC; ++z) {
+        const double dz = node_coord(q2 + z - m, C.h, sz[i]);
+        if (sq_add(dxy2, dz) < srp2[i]) {
+          any = true;
+          ++pairs;
+          if (cx == m && cy == m && z == m) ++near;
+        }
+      }
+      if (any) ++count;
+    }
+    atomicMax(&colmax, count);
+    if (near) atomicAdd(&nnear, near);
+    if (pairs) atomicAdd(&npairs, (unsigned long long)pairs);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    atomicMax(&stats[4 * ci + 0], found);
+    atomicMax(&stats[4 * ci + 1], colmax);
+    atomicMax(&stats[4 * ci + 2], nnear);
+    atomicAdd(reinterpret_cast<unsigned long long*>(pair_total) + ci, npairs);
+  }
+}
+
+
+// Number of eigenvalues of the tridiagonal (a, b) below x (Sturm count).
+__device__ int sturm_count(const double* a, const double* b, int n, double x) {
+  int c = 0;
+  double d = a[0] - x;
+  if (d < 0) ++c;
+  for (int i = 1; i < n; ++i) {
+    if (d == 0.0) d = -1e-300;
+    d = a[i] - x - b[i - 1] * b[i - 1] / d;
+    if (d < 0) ++c;
+  }
+  return c;
+}
+
+// Square of the last component of the unit eigenvector of eigenvalue x:
+// p_{n-1}(x) / p_n'(x) with p_k the characteristic polynomials of the
+// leading k x k blocks (three-term recurrence, rescaled against overflow).
+__device__ double last_component_sq(const double* a, const double* b, int n, double x) {
+  double pm2 = 1.0, pm1 = x - a[0];
+  double dm2 = 0.0, dm1 = 1.0;
+  for (int k = 1; k < n; ++k) {
+    const double bb = b[k - 1] * b[k - 1];
+    const double p = (x - a[k]) * pm1 - bb * pm2;
+    const double d = pm1 + (x - a[k]) * dm1 - bb * dm2;
+    pm2 = pm1;
+    pm1 = p;
+    dm2 = dm1;
+    dm1 = d;
+    const double mx = fmax(fabs(pm1), fabs(dm1));
+    if (mx > 1e150) {
+      pm1 *= 1e-150;
+      pm2 *= 1e-150;
+      dm1 *= 1e-150;
+      dm2 *= 1e-150;
+    }
+  }
+  // p_{n-1} = pm2, p_n' = dm1
+  return pm2 / dm1;
+}
+
+__global__ void k_bounds(PlanDev P, const long long* items, const int* item_cell, long long nitems) {
+  const long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (it >= nitems) return;
+  const long long g = items[it];
+  const double* lan = P.lan + g * (2 * SQ_KL_MAX);
+  const int n = P.lan_steps[g];
+  const double* a = lan;
+  const double* b = lan + SQ_KL_MAX;
+  double lo, hi;
+  if (n <= 1) {
+    lo = a[0] - b[0];
+    hi = a[0] + b[0];
+  } else {
+    // Gershgorin interval
+    double glo = a[0] - fabs(b[0]), ghi = a[0] + fabs(b[0]);
+    for (int i = 1; i < n; ++i) {
+      const double r = fabs(b[i - 1]) + (i < n - 1 ? fabs(b[i]) : 0.0);
+      glo = fmin(glo, a[i] - r);
+      ghi = fmax(ghi, a[i] + r);
+    }
+    const double pad = 1e-12 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
+    glo -= pad;
+    ghi += pad;
+    // smallest eigenvalue: count(x) goes 0 -> 1
+    double l = glo, u = ghi;
+    for (int i = 0; i < 200; ++i) {
+      const double mid = 0.5 * (l + u);
+      if (mid <= l || mid >= u) break;
+      if (sturm_count(a, b, n, mid) >= 1) u = mid; else l = mid;
+    }
+    const double tmin = 0.5 * (l + u);
+    // largest eigenvalue: count(x) goes n-1 -> n
+    l = glo;
+    u = ghi;
+    for (int i = 0; i < 200; ++i) {
+      const double mid = 0.5 * (l + u);
+      if (mid <= l || mid >= u) break;
+      if (sturm_count(a, b, n, mid) >= n) u = mid; else l = mid;
+    }
+    const double tmax = 0.5 * (l + u);
+    const double smin = sqrt(fabs(last_component_sq(a, b, n, tmin)));
+    const double smax = sqrt(fabs(last_component_sq(a, b, n, tmax)));
+    lo = tmin - b[n - 1] * smin;
+    hi = tmax + b[n - 1] * smax;
+  }
+  double* bd = P.bnd + 4 * g;
+  bd[0] = lo;
+  bd[1] = hi;
+  bd[2] = 0.5 * (hi + lo);
+  bd[3] = 0.5 * (hi - lo);
+}
+
+// ---------------------------------------------------------------------------
+// Clenshaw-Curtis coefficients and the Fermi level (Sec. IV, App. A)
+//
+// c_j = (2/M) sum_k g(cos th_k) cos(j th_k), th_k = pi (k + 1/2) / M.  Off a
+// window of +-40 kT around mu the FP64 occupation is exactly 0 or 1, so the
+// sum splits into a closed-form tail  sum_{k >= a} cos(j th_k) =
+//   sin((M - a) j pi / 2M) cos((a + M) j pi / 2M) / sin(j pi / 2M)
+// and the window points.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double tail_cos_sum(int j, int a, int M) {
+  if (a >= M) return 0.0;
+  if (j == 0) return (double)(M - a);
+  const double tm = 2.0 * (double)M;
+  return sinpi((double)(M - a) * j / tm) * cospi((double)(a + M) * j / tm) / sinpi((double)j / tm);
+}
+
+struct Window {
+  int M, kb, ka;
+  double muh, sigh;
+};
+
+__device__ __forceinline__ Window fermi_window(double mu, double chi, double zeta, double kT, int npl) {
+  Window W;
+  W.M = quad_points(zeta, kT, npl);
+  W.muh = (mu - chi) / zeta;
+  W.sigh = kT / zeta;
+  const double xb = W.muh + 40.0 * W.sigh;   // above: occupation 0
+  const double xa = W.muh - 40.0 * W.sigh;   // below: occupation 1
+  const double M = (double)W.M;
+  // x_k <= xb  <=>  k >= M acos(xb)/pi - 1/2
+  int kb = xb >= 1.0 ? 0 : (xb <= -1.0 ? W.M : (int)floor(M * acos(xb) / M_PI - 0.5) - 1);
+  int ka = xa <= -1.0 ? W.M - 1 : (xa >= 1.0 ? -1 : (int)ceil(M * acos(xa) / M_PI - 0.5) + 1);
+  W.kb = kb < 0 ? 0 : (kb > W.M ? W.M : kb);
+  W.ka = ka > W.M - 1 ? W.M - 1 : (ka < -1 ? -1 : ka);
+  return W;
+}
+
+__device__ __forceinline__ double occupation(double x, const Window& W) {
+  return 0.5 * (1.0 - tanh((x - W.muh) / (2.0 * W.sigh)));
+}
+
+// One wave per node: N_q(mu) = sum'_j c_q^j(mu) rho_q^j.
+__global__ void __launch_bounds__(256) k_mu_eval(PlanDev P, const long long* items,
+                                                 const int* item_cell, long long nitems) {
+  __shared__ double smom[4][260];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long it = blockIdx.x * 4ll + wv;
+  if (it >= nitems) return;   // whole wave leaves; only wave-level syncs below
+  const long long g = items[it];
+  const int ci = item_cell[it];
+  const double* mus = P.mus + 8 * ci;
+  if (mus[MU_DONE] != 0.0) return;
+  const CellDev& C = P.cells[ci];
+  const int npl = C.npl;
+  const double* mom = P.mom + g * P.mstride;
+  for (int j = lane; j <= npl; j += 64) smom[wv][j] = mom[j];
+  wave_sync();
+  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+  const Window W = fermi_window(mus[MU_MID], chi, zeta, C.kT, npl);
+  double acc = 0.0;
+  // occupied tail: sum'_j rho^j S_j(ka + 1)
+  for (int j = lane; j <= npl; j += 64) {
+    const double r = j == 0 ? 0.5 * smom[wv][0] : smom[wv][j];
+    acc += r * tail_cos_sum(j, W.ka + 1, W.M);
+  }
+  // window points: g_k * sum'_j rho^j T_j(x_k) (Clenshaw)
+  for (int k = W.kb + lane; k <= W.ka; k += 64) {
+    const double x = cospi(((double)k + 0.5) / (double)W.M);
+    const double occ = occupation(x, W);
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = npl; j >= 1; --j) {
+      const double b0 = smom[wv][j] + 2.0 * x * b1 - b2;
+      b2 = b1;
+      b1 = b0;
+    }
+    const double R = 0.5 * smom[wv][0] + x * b1 - b2;
+    acc += occ * R;
+  }
+  acc = warp_sum(acc);
+  if (lane == 0) P.nq[g] = (2.0 / (double)W.M) * acc;
+}
+
+// One wave per node: c_j, d_j at the final mu, rho_q and e_q.
+__global__ void __launch_bounds__(256) k_coeffs(PlanDev P, const long long* items,
+                                                const int* item_cell, long long nitems) {
+  __shared__ double sg[4][256];
+  __shared__ double sc[4][264];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long it = blockIdx.x * 4ll + wv;
+  const bool live = it < nitems;
+  const long long g = live ? items[it] : 0;
+  const int ci = live ? item_cell[it] : 0;
+  const CellDev& C = P.cells[ci];
+  const int npl = C.npl;
+  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+  const double mu = P.mus[8 * ci + MU_VAL];
+  const Window W = fermi_window(mu, chi, zeta, C.kT, npl);
+  const double* mom = P.mom + g * P.mstride;
+  // per lane: coefficients j = lane + 64 r
+  double cacc[5] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < 5; ++r) {
+    const int j = lane + 64 * r;
+    if (j <= npl + 1) cacc[r] = tail_cos_sum(j, W.ka + 1, W.M);
+  }
+  for (int base = W.kb; base <= W.ka; base += 256) {
+    // occupations of 256 window points into LDS
+    for (int t = lane; t < 256; t += 64) {
+      const int k = base + t;
+      double o = 0.0;
+      if (k <= W.ka) o = occupation(cospi(((double)k + 0.5) / (double)W.M), W);
+      sg[wv][t] = o;
+    }
+    wave_sync();
+    const int kend = min(base + 256, W.ka + 1);
+    for (int r = 0; r < 5; ++r) {
+      const int j = lane + 64 * r;
+      if (j > npl + 1) break;
+      double a = 0.0;
+      for (int k = base; k < kend; ++k) a += sg[wv][k - base] * cospi((double)j * ((double)k + 0.5) / (double)W.M);
+      cacc[r] += a;
+    }
+    wave_sync();
+  }
+  const double f = 2.0 / (double)W.M;
+  for (int r = 0; r < 5; ++r) {
+    const int j = lane + 64 * r;
+    if (j <= npl + 1) sc[wv][j] = f * cacc[r];
+  }
+  wave_sync();
+  if (!live) return;
+  double rs = 0.0, es = 0.0;
+  for (int j = lane; j <= npl; j += 64) {
+    const double cj = sc[wv][j];
+    const double dj = 0.5 * (sc[wv][j + 1] + sc[wv][j == 0 ? 1 : j - 1]);
+    const double wgt = j == 0 ? 0.5 : 1.0;
+    rs += wgt * cj * mom[j];
+    es += wgt * (chi * cj + zeta * dj) * mom[j];
+    P.coef[g * P.mstride + j] = cj;
+  }
+  rs = warp_sum(rs);
+  es = warp_sum(es);
+  if (lane == 0) {
+    P.rec[g * SQ_REC + 0] = 2.0 / C.dV * rs;
+    P.rec[g * SQ_REC + 1] = 2.0 * es;
+  }
+}
+
+// Neumaier-compensated fixed-order sum of x[i * stride] over [0, n).
+__device__ void block_neumaier(const double* x, long long n, long long stride, double* out,
+                               double* red_s, double* red_c) {
+  double s = 0.0, c = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = x[i * stride];
+    const double t = s + v;
+    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  red_s[threadIdx.x] = s;
+  red_c[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, Cc = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) {
+      const double v = red_s[i];
+      const double t = S + v;
+      Cc += fabs(S) >= fabs(v) ? (S - t) + v : (v - t) + S;
+      S = t;
+      Cc += red_c[i];
+    }
+    *out = S + Cc;
+  }
+  __syncthreads();
+}
+
+// Fermi-level bracket: [min lam_lo - 40 kT, max lam_hi + 40 kT].
+__global__ void __launch_bounds__(256) k_mu_init(PlanDev P, const int* cells, const int* fixed_mode) {
+  __shared__ double slo[256], shi[256];
+  const int ci = cells[blockIdx.x];
+  const CellDev& C = P.cells[ci];
+  double lo = 1e300, hi = -1e300;
+  for (long long q = threadIdx.x; q < C.Nd; q += blockDim.x) {
+    const double* b = P.bnd + 4 * (C.node_base + q);
+    lo = fmin(lo, b[0]);
+    hi = fmax(hi, b[1]);
+  }
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 256; ++i) {
+      lo = fmin(lo, slo[i]);
+      hi = fmax(hi, shi[i]);
+    }
+    double* m = P.mus + 8 * ci;
+    m[MU_LO] = lo - 40.0 * C.kT;
+    m[MU_HI] = hi + 40.0 * C.kT;
+    m[MU_IT] = 0.0;
+    m[MU_N] = 0.0;
+    if (fixed_mode[blockIdx.x]) {
+      m[MU_DONE] = 1.0;
+      m[MU_PHASE] = 3.0;
+      m[MU_VAL] = C.mu0;
+      m[MU_MID] = C.mu0;
+    } else {
+      m[MU_DONE] = 0.0;
+      m[MU_PHASE] = 0.0;
+      m[MU_MID] = m[MU_LO];
+    }
+  }
+}
+
+// Electron count of each cell at its trial mu and the bisection update.
+__global__ void __launch_bounds__(256) k_mu_step(PlanDev P, const int* cells) {
+  __shared__ double rs[256], rc[256];
+  __shared__ double tot;
+  const int ci = cells[blockIdx.x];
+  const CellDev& C = P.cells[ci];
+  double* m = P.mus + 8 * ci;
+  if (m[MU_DONE] != 0.0) return;
+  block_neumaier(P.nq + C.node_base, C.Nd, 1, &tot, rs, rc);
+  if (threadIdx.x != 0) return;
+  const double N = 2.0 * tot;
+  const double Ne = C.ne;
+  m[MU_N] = N;
+  const int phase = (int)m[MU_PHASE];
+  if (phase == 0) {
+    if (!(N < Ne)) { m[MU_DONE] = 2.0; return; }
+    m[MU_PHASE] = 1.0;
+    m[MU_MID] = m[MU_HI];
+    return;
+  }
+  if (phase == 1) {
+    if (!(Ne < N)) { m[MU_DONE] = 2.0; return; }
+    m[MU_PHASE] = 2.0;
+    m[MU_MID] = 0.5 * (m[MU_LO] + m[MU_HI]);
+    return;
+  }
+  const double mid = m[MU_MID];
+  if (fabs(N - Ne) <= 1e-13 * Ne) {
+    m[MU_VAL] = mid;
+    m[MU_DONE] = 1.0;
+    return;
+  }
+  if (N < Ne) m[MU_LO] = mid; else m[MU_HI] = mid;
+  m[MU_IT] += 1.0;
+  if (m[MU_IT] >= 200.0) {
+    m[MU_VAL] = 0.5 * (m[MU_LO] + m[MU_HI]);
+    m[MU_DONE] = 1.0;
+    return;
+  }
+  m[MU_MID] = 0.5 * (m[MU_LO] + m[MU_HI]);
+}
+
+__global__ void __launch_bounds__(256) k_reduce(PlanDev P, const int* cells, int col0, int ncol) {
+  __shared__ double rs[256], rc[256];
+  const int ci = cells[blockIdx.x];
+  const CellDev& C = P.cells[ci];
+  for (int c = col0; c < col0 + ncol; ++c) {
+    block_neumaier(P.rec + C.node_base * SQ_REC + c, C.Nd, SQ_REC, P.sums + ci * (SQ_REC + 4) + c,
+                   rs, rc);
+  }
+}
+
+// Local potential on the periodic grid: sum over atom images within v_rcut.
+__global__ void __launch_bounds__(256) k_vloc(const CellDev* cell, double* out) {
+  const CellDev& C = *cell;
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= C.Nd) return;
+  const long long ix = i % C.n[0], iy = (i / C.n[0]) % C.n[1], iz = i / ((long long)C.n[0] * C.n[1]);
+  double v = 0.0;
+  for (int I = 0; I < C.nimg; ++I) {
+    const double* R = C.img + 4 * I;
+    const SpecDev& s = C.sp[(int)R[3]];
+    const double dx = node_coord(ix, C.h, R[0]);
+    const double dy = node_coord(iy, C.h, R[1]);
+    const double dz = node_coord(iz, C.h, R[2]);
+    const double r2 = sq_add(sq_sum2(dx, dy), dz);
+    if (r2 < s.v_rc * s.v_rc) v += -s.v_amp * exp(-r2 / (2.0 * s.v_sig * s.v_sig));
+  }
+  out[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers.  The file is compiled once per cube width (SQ_ONE_NC defined:
+// the templated recurrence kernels of that width) and once without it (the
+// width-independent kernels and the dispatch over widths), so that the
+// widths build in parallel.  Within a width the variant is picked from the
+// slot capacity kc the cell needs (largest number of atom images crossing
+// one z-column of a cube, measured at set-up).
+// ---------------------------------------------------------------------------
+#define SQ_NC_LIST(X) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25)
+
+#define SQ_DECL_NC(N)                                                                          \
+  hipError_t sq_launch_lanczos_##N(int kc, const PlanDev& P, const long long* items,          \
+                                   const int* ic, long long n, hipStream_t s);                \
+  hipError_t sq_launch_moments_##N(bool fp64, int kc, const PlanDev& P, const long long* items, \
+                                   const int* ic, long long n, hipStream_t s);                \
+  hipError_t sq_launch_stress_##N(bool fp64, int kc, const PlanDev& P, const long long* items,  \
+                                  const int* ic, long long n, hipStream_t s);                 \
+  hipError_t sq_launch_census_##N(const PlanDev& P, const long long* items, const int* ic,     \
+                                  long long n, int* stats, long long* pairs, hipStream_t s);
+SQ_NC_LIST(SQ_DECL_NC)
+
+// Largest slot capacity per precision and width (0: unsupported).
+__host__ __device__ constexpr int sq_kc_max(bool fp64, int nc) {
+  return fp64 ? (nc <= 21 ? 48 : 24) : 48;
+}
+
+#ifdef SQ_ONE_NC
+#define SQ_CAT2(a, b) a##b
+#define SQ_CAT(a, b) SQ_CAT2(a, b)
+// Everything below that depends on the width has internal linkage: the
+// units of the other widths define templates of the same names, and weak
+// (COMDAT) instantiations would otherwise be merged across widths.
+namespace {
+constexpr int SQN = SQ_ONE_NC;
+
+enum Fam { FAM_LAN, FAM_MOM, FAM_STR };
+
+template <class Vr, int F>
+hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, long long n,
+                      hipStream_t s) {
+  const dim3 grid((unsigned)n), block(Geo<Vr::NC>::NT);
+  if constexpr (F == FAM_LAN)
+    hipLaunchKernelGGL(k_lanczos<Vr>, grid, block, 0, s, P, items, ic);
+  else if constexpr (F == FAM_MOM)
+    hipLaunchKernelGGL(k_moments<Vr>, grid, block, 0, s, P, items, ic);
+  else
+    hipLaunchKernelGGL(k_stress<Vr>, grid, block, 0, s, P, items, ic);
+  return hipGetLastError();
+}
+
+template <int F>
+hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
+                       hipStream_t s) {
+  if (kc <= 16) return launch_var<Var<double, SQN, 16, false>, F>(P, items, ic, n, s);
+  if (kc <= 24) return launch_var<Var<double, SQN, 24, false>, F>(P, items, ic, n, s);
+  if constexpr (SQN <= 21) {
+    if (kc <= 48) return launch_var<Var<double, SQN, 48, true>, F>(P, items, ic, n, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int F>
+hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
+                       hipStream_t s) {
+  if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F>(P, items, ic, n, s);
+  if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F>(P, items, ic, n, s);
+  if (kc <= 48) return launch_var<Var<float, SQN, 48, true>, F>(P, items, ic, n, s);
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t SQ_CAT(sq_launch_lanczos_, SQ_ONE_NC)(int kc, const PlanDev& P, const long long* items,
+                                                const int* ic, long long n, hipStream_t s) {
+  return launch_fp64<FAM_LAN>(kc, P, items, ic, n, s);
+}
+
+hipError_t SQ_CAT(sq_launch_moments_, SQ_ONE_NC)(bool fp64, int kc, const PlanDev& P,
+                                                const long long* items, const int* ic, long long n,
+                                                hipStream_t s) {
+  return fp64 ? launch_fp64<FAM_MOM>(kc, P, items, ic, n, s)
+              : launch_fp32<FAM_MOM>(kc, P, items, ic, n, s);
+}
+
+hipError_t SQ_CAT(sq_launch_stress_, SQ_ONE_NC)(bool fp64, int kc, const PlanDev& P,
+                                               const long long* items, const int* ic, long long n,
+                                               hipStream_t s) {
+  return fp64 ? launch_fp64<FAM_STR>(kc, P, items, ic, n, s)
+              : launch_fp32<FAM_STR>(kc, P, items, ic, n, s);
+}
+
+hipError_t SQ_CAT(sq_launch_census_, SQ_ONE_NC)(const PlanDev& P, const long long* items,
+                                               const int* ic, long long n, int* stats,
+                                               long long* pairs, hipStream_t s) {
+  hipLaunchKernelGGL(k_census<SQN>, dim3((unsigned)n), dim3(Geo<SQN>::NT), 0, s, P, items, ic, stats,
+                     pairs);
+  return hipGetLastError();
+}
+
+#else  // width-independent part
+
+bool sq_nc_supported(int nc) {
+#define SQ_CASE(N) if (nc == N) return true;
+  SQ_NC_LIST(SQ_CASE)
+#undef SQ_CASE
+  return false;
+}
+
+int sq_kc_limit(bool fp64, int nc) { return sq_kc_max(fp64, nc); }
+
+hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
+                             const int* item_cell, long long nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define SQ_CASE(N) if (nc == N) return sq_launch_lanczos_##N(kc, P, items, item_cell, nitems, s);
+  SQ_NC_LIST(SQ_CASE)
+#undef SQ_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t sq_launch_moments(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
+                             const int* item_cell, long long nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define SQ_CASE(N) \
+  if (nc == N) return sq_launch_moments_##N(fp64, kc, P, items, item_cell, nitems, s);
+  SQ_NC_LIST(SQ_CASE)
+#undef SQ_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t sq_launch_stress(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
+                            const int* item_cell, long long nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define SQ_CASE(N) \
+  if (nc == N) return sq_launch_stress_##N(fp64, kc, P, items, item_cell, nitems, s);
+  SQ_NC_LIST(SQ_CASE)
+#undef SQ_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
+                            long long nitems, int* stats, long long* pairs, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define SQ_CASE(N) \
+  if (nc == N) return sq_launch_census_##N(P, items, item_cell, nitems, stats, pairs, s);
+  SQ_NC_LIST(SQ_CASE)
+#undef SQ_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s) {
+  const long long nb = (h_cell.Nd + 255) / 256;
+  hipLaunchKernelGGL(k_vloc, dim3((unsigned)nb), dim3(256), 0, s, d_cell, vloc);
+  return hipGetLastError();
+}
+
+hipError_t sq_launch_bounds(const PlanDev& P, const long long* items, const int* item_cell,
+                            long long nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bounds, dim3((unsigned)((nitems + 127) / 128)), dim3(128), 0, s, P, items,
+                     item_cell, nitems);
+  return hipGetLastError();
+}
+
+hipError_t sq_launch_mu_init(const PlanDev& P, const int* cells, int ncells, const int* fixed_mode,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_init, dim3(ncells), dim3(256), 0, s, P, cells, fixed_mode);
+  return hipGetLastError();
+}
+
+hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int* item_cell,
+                             long long nitems, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_eval, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, P, items,
+                     item_cell, nitems);
+  return hipGetLastError();
+}
+
+hipError_t sq_launch_mu_step(const PlanDev& P, const int* cells, int ncells, hipStream_t s) {
+  hipLaunchKernelGGL(k_mu_step, dim3(ncells), dim3(256), 0, s, P, cells);
+  return hipGetLastError();
+}
+
+hipError_t sq_launch_coeffs(const PlanDev& P, const long long* items, const int* item_cell,
+                            long long nitems, hipStream_t s) {
+  hipLaunchKernelGGL(k_coeffs, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, P, items,
+                     item_cell, nitems);
+  return hipGetLastError();
+}
+
+hipError_t sq_launch_reduce(const PlanDev& P, const int* cells, int ncells, int col0, int ncol,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(ncells), dim3(256), 0, s, P, cells, col0, ncol);
+  return hipGetLastError();
+}
+
+#endif
