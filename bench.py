@@ -118,11 +118,25 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1536,
                     help="nodes in the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: "
+                         "the reference for scaling the HBM byte counters of a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; a multi-GPU run (%d) is not part of it"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        import torch
+        n = args.copy_probe * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
+        return
 
     from paper_2006_03697_amd import sq
     from paper_2006_03697_amd import workloads as W

@@ -558,9 +558,11 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
       const std::string tag = "cell " + std::to_string(i) + ": ";
       // the FP64 Lanczos runs in every precision mode
       const int kc_lim = std::min(sq_kc_limit(true, c.nc), sq_kc_limit(fp64, c.nc));
-      if (c.census_img > 112)
+      const int img_lim = sq_img_limit(c.nc);
+      if (c.census_img > img_lim)
         st = fail(p, SQ_E_ARG, tag + std::to_string(c.census_img) +
-                                   " atom images reach one cube (at most 112 supported)");
+                                   " atom images reach one cube (at most " +
+                                   std::to_string(img_lim) + " supported)");
       else if (c.census_col > kc_lim)
         st = fail(p, SQ_E_ARG, tag + std::to_string(c.census_col) +
                                    " atom images cross one cube column (at most " +

@@ -91,6 +91,7 @@ hipError_t sq_launch_stress(int nc, int kc, bool fp64, const PlanDev& P, const l
 hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, int* stats, long long* pairs, hipStream_t s);
 int sq_kc_limit(bool fp64, int nc);
+int sq_img_limit(int nc);
 hipError_t sq_launch_reduce(const PlanDev& P, const int* cells, int ncells, int col0, int ncol,
                             hipStream_t s);
 bool sq_nc_supported(int nc);

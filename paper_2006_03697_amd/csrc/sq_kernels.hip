@@ -47,6 +47,7 @@ template <typename U>
 __device__ __forceinline__ void opaque(U&) {}
 #else
 __device__ __forceinline__ void opaque(int& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(unsigned& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void opaque(float& x) {
   unsigned u = __float_as_uint(x);
   asm volatile("" : "+v"(u));
@@ -72,28 +73,6 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
-// Fixed-order block sum of two values (deterministic); red has 2*NW slots.
-template <int NW>
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
-  a = warp_sum(a);
-  b = warp_sum(b);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  if (l == 0) {
-    red[w] = a;
-    red[NW + w] = b;
-  }
-  __syncthreads();
-  double sa = 0.0, sb = 0.0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    sa += red[i];
-    sb += red[NW + i];
-  }
-  __syncthreads();
-  a = sa;
-  b = sb;
-}
-
 __device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
   double t = ceil(8.0 * zeta / kT);
   double tgt = fmax((double)(4 * (npl + 2)), t);
@@ -102,67 +81,119 @@ __device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
   return M;
 }
 
-template <int NC>
-struct Geo {
-  static constexpr int NC2 = NC * NC;
-  static constexpr int NC3 = NC2 * NC;
-  static constexpr int NT = ((NC2 + 63) / 64) * 64;
+// ---------------------------------------------------------------------------
+// Cube layout in LDS and the thread <-> z-column map
+//
+// Thread (cx, cy) owns the z-column (cx, cy) of the cube: the current and
+// previous Chebyshev vectors and the diagonal live in its registers, and the
+// current vector is mirrored in LDS for the x and y neighbours of the
+// stencil.  Padded layout: rows of RS >= NC + 6 elements (the tail zero) and
+// planes of NC + 6 rows (the last 6 zero), after 6 zero rows and 6 zeros, so
+// every neighbour outside the cube reads a zero and needs no predicate.
+//
+// LDS has 32 banks of 4 bytes: a 32-bit access by 32 lanes, or a 64-bit
+// access by 16 lanes, is conflict-free when the element addresses are
+// distinct modulo 32 (resp. 16).  With the padded row stride consecutive
+// rows alias, so lanes are mapped to columns by address residue instead of
+// row-major: lane 32 g + r owns the g-th column (in row-major order) whose
+// row offset cy * RS + cx is congruent to r modulo 32.  Every access of a
+// wave is then a constant shift of these offsets, hence conflict-free.  RS
+// is the smallest stride for which no residue class has more columns than
+// the block has 32-lane groups.
+// ---------------------------------------------------------------------------
+constexpr int sq_residue_max(int nc, int rs) {
+  int cnt[32] = {};
+  int mx = 0;
+  for (int cy = 0; cy < nc; ++cy)
+    for (int cx = 0; cx < nc; ++cx) {
+      const int r = (cy * rs + cx) & 31;
+      if (++cnt[r] > mx) mx = cnt[r];
+    }
+  return mx;
+}
+
+constexpr int sq_threads(int nc) { return ((nc * nc + 63) / 64) * 64; }
+
+constexpr int sq_pick_rs(int nc) {
+  for (int rs = nc + SQ_FDM; rs <= nc + SQ_FDM + 16; ++rs)
+    if (sq_residue_max(nc, rs) * 32 <= sq_threads(nc)) return rs;
+  return 0;
+}
+
+template <int NC, bool PAD>
+struct Lay {
+  static constexpr int NT = sq_threads(NC);
   static constexpr int NW = NT / 64;
   static constexpr int MH = NC / 2;
+  static constexpr int RS = PAD ? sq_pick_rs(NC) : NC;              // row stride
+  static constexpr int PL = PAD ? (NC + SQ_FDM) * RS : NC * NC;     // plane stride
+  static constexpr int X0 = PAD ? SQ_FDM * RS + SQ_FDM : 0;         // offset of (0, 0, 0)
+  static constexpr int SIZE = X0 + NC * PL;
+  static_assert(!PAD || RS > 0, "no conflict-free row stride");
+  __device__ static constexpr int at(int x, int y, int z) { return X0 + z * PL + y * RS + x; }
+
+  // Column of thread tid (see above); inactive threads own no column.
+  __device__ static void column(int tid, int& cx, int& cy, bool& active) {
+    cx = 0;
+    cy = 0;
+    active = false;
+    if constexpr (PAD) {
+      const int r = tid & 31, g = tid >> 5;
+      int seen = 0;
+      for (int y = 0; y < NC; ++y) {
+        const int x = (r - y * RS) & 31;   // the one column of row y with residue r
+        if (x < NC) {
+          if (seen == g) {
+            cx = x;
+            cy = y;
+            active = true;
+          }
+          ++seen;
+        }
+      }
+    } else {
+      active = tid < NC * NC;
+      cx = tid % NC;
+      cy = tid / NC;
+    }
+  }
 };
 
-// A kernel variant: working precision T, cube width NC, KC image slots per
-// z-column, and where the xy factor of a projector on a column comes from
-// (SEP: product of two per-image tables in LDS; otherwise a register per
-// slot).  The LDS layout of the cube vector is padded with zero halos when
-// the whole working set still fits the 160 KiB of LDS.
-template <typename T_, int NC_, int KC_, bool SEP_>
+// A kernel variant: working precision T, cube width NC, KC projector slots
+// per z-column, and whether each slot's weight on plane 0 is kept in a
+// register (AREG) or recomputed at every use.  The padded LDS layout is used
+// when the whole working set fits the 160 KiB of LDS.
+template <typename T_, int NC_, int KC_, bool AREG_>
 struct Var {
   using T = T_;
   static constexpr int NC = NC_;
   static constexpr int KC = KC_;
-  static constexpr bool SEP = SEP_;
-  static constexpr int NIMG = sizeof(T_) == 4 ? 160 : 112;
-  static constexpr int NEAR = 32;
-  static constexpr int PRS = NC_ + SQ_FDM;
-  static constexpr int PPL = (NC_ + SQ_FDM) * PRS;
-  static constexpr size_t OTHER = sizeof(T_) * (size_t)NIMG * NC_ * (SEP_ ? 3 : 1) +
-                                  8 * (size_t)NIMG * 8 + (size_t)NEAR * 11 * 8 + NEAR * 4 + 1024;
-  static constexpr size_t PADDED = sizeof(T_) * (size_t)(SQ_FDM * PRS + SQ_FDM + NC_ * PPL);
+  static constexpr bool AREG = AREG_;
+  // slot word: chord bits 31 .. 32 - NC, image index below
+  static constexpr int IBITS = 32 - NC_;
+  static constexpr int NIMG = (1 << IBITS) < 160 ? (1 << IBITS) : 160;
+  static constexpr int NEAR = SQ_NEAR_MAX;
+  static constexpr size_t OTHER = 8 * (size_t)NIMG * 11 + (size_t)NEAR * 11 * 8 + NEAR * 4 + 1024;
 #ifdef SQ_NO_PAD
   static constexpr bool PAD = false;
 #else
-  static constexpr bool PAD = PADDED + OTHER <= 163840;
+  static constexpr bool PAD = sizeof(T_) * (size_t)Lay<NC_, true>::SIZE + OTHER <= 163840;
 #endif
-};
-
-// LDS layout of one cube vector.  Padded: every row is followed by SQ_FDM
-// zero columns and every plane by SQ_FDM zero rows, and the array starts
-// with SQ_FDM zero rows plus SQ_FDM zeros, so x and y neighbours outside the
-// cube read zeros and need no predicate.
-template <class Vr>
-struct Lay {
-  static constexpr int NC = Vr::NC;
-  static constexpr bool PAD = Vr::PAD;
-  static constexpr int RS = PAD ? Vr::PRS : NC;                    // row stride
-  static constexpr int PL = PAD ? Vr::PPL : NC * NC;               // plane stride
-  static constexpr int X0 = PAD ? SQ_FDM * Vr::PRS + SQ_FDM : 0;   // offset of (0,0,0)
-  static constexpr int SIZE = X0 + NC * PL;
-  __device__ static constexpr int at(int x, int y, int z) { return X0 + z * PL + y * RS + x; }
+  using L = Lay<NC_, PAD>;
 };
 
 template <class Vr>
 struct Smem {
   using T = typename Vr::T;
   static constexpr int NI = Vr::NIMG;
-  T tl[Lay<Vr>::SIZE];
-  T ez[NI][Vr::NC];
-  T ex[Vr::SEP ? NI : 1][Vr::NC];
-  T ey[Vr::SEP ? NI : 1][Vr::NC];
-  double ix[NI], iy[NI], iz[NI];
-  double rp2[NI], i2s[NI], gdv[NI];
-  double pacc[2][NI];
-  double red[2 * 16];
+  T tl[Vr::L::SIZE];
+  double ix[NI], iy[NI], iz[NI];      // image positions (unwrapped)
+  double rp2[NI], i2s[NI], gdv[NI];   // r_p^2, 1 / (2 sigma_p^2), gamma dV
+  // z factor of each image on the cube planes: e(z) = exp(-u_z^2 i2s) with
+  // u_z = u_0 + z h, generated as e(z + 1) = e(z) rr(z), rr(z + 1) = rr(z) cq
+  double e0[NI], r0[NI], cq[NI];
+  double pacc[2][NI];                 // projections, double-buffered over steps
+  double red[2][2 * 16];              // block sums, double-buffered over steps
   double near_chi[Vr::NEAR];
   double nsum[Vr::NEAR][10];
   int near_img[Vr::NEAR];
@@ -177,18 +208,26 @@ struct Ctx {
   int cx, cy, col;
   bool active;
   long long q0, q1, q2;
-  int nslot;
-  int sid[Vr::KC];                  // image | z0 << 8 | z1 << 16
-  T sexy[Vr::SEP ? 1 : Vr::KC];     // xy factor of the projector (register variant)
-  T vd[Vr::NC];                     // diagonal of (H_q - shift) without the stencil centre
+  int nslot;    // slots of this column
+  int nsw;      // largest slot count in the wave (wave-uniform)
+  // slot s: bit 31 - z set for the planes z of the chord of the image's
+  // spherical support on this column; the image index in the low bits
+  unsigned sid[Vr::KC];
+  double a0[Vr::AREG ? Vr::KC : 1];   // projector value of slot s at (cx, cy, plane 0)
+  T vd[Vr::NC];                       // diagonal of (H_q - shift) without the stencil centre
 };
 
 template <class Vr>
-__device__ __forceinline__ typename Vr::T slot_exy(const Smem<Vr>& S, const Ctx<Vr>& X, int s, int i) {
-  if constexpr (Vr::SEP)
-    return S.ex[i][X.cx] * S.ey[i][X.cy];
-  else
-    return X.sexy[s];
+__device__ __forceinline__ double slot_start(const Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C,
+                                             int s, int i) {
+  if constexpr (Vr::AREG) {
+    return X.a0[s];
+  } else {
+    constexpr int m = Vr::NC / 2;
+    const double dx = node_coord(X.q0 + X.cx - m, C.h, S.ix[i]);
+    const double dy = node_coord(X.q1 + X.cy - m, C.h, S.iy[i]);
+    return exp(-sq_sum2(dx, dy) * S.i2s[i]) * S.e0[i];
+  }
 }
 
 // Image list of the node's cube: the tile list filtered by distance to the
@@ -247,19 +286,24 @@ __device__ __forceinline__ int gather_images(const CellDev& C, long long q0, lon
   return total;   // may exceed CAP (then only CAP were stored and err is set)
 }
 
-// Node prologue: image list of the cube, projector factor tables, per-column
-// chords, diagonal.  shift is subtracted from the diagonal.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Node prologue: image list of the cube, z-factor constants, per-column
+// chords and projector weights, diagonal.  shift is subtracted from the
+// diagonal.
 template <class Vr>
 __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, double shift,
                                               Smem<Vr>& S, Ctx<Vr>& X, unsigned* err) {
   using T = typename Vr::T;
+  using L = typename Vr::L;
   constexpr int NC = Vr::NC;
-  using G = Geo<NC>;
-  const int m = G::MH;
+  constexpr int m = L::MH;
   const int tid = threadIdx.x;
-  X.cx = tid % NC;
-  X.cy = tid / NC;
-  X.active = tid < G::NC2;
+  L::column(tid, X.cx, X.cy, X.active);
   X.col = X.cx + NC * X.cy;
   X.q0 = q % C.n[0];
   X.q1 = (q / C.n[0]) % C.n[1];
@@ -276,37 +320,38 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     S.i2s[pos] = 1.0 / (2.0 * s.p_sig * s.p_sig);
     S.gdv[pos] = s.gamma * C.dV;
   };
-  const int found = gather_images<G::NT, G::NW, Vr::NIMG>(C, X.q0, X.q1, X.q2, m, &S.nimg,
+  const int found = gather_images<L::NT, L::NW, Vr::NIMG>(C, X.q0, X.q1, X.q2, m, &S.nimg,
                                                            S.wcnt, store, err);
   const int nimg = found < Vr::NIMG ? found : Vr::NIMG;
   if (tid == 0) S.nimg = nimg;
 
-  // ---- separable factors of every image on the cube's planes / columns ----
-  for (int idx = tid; idx < nimg * NC; idx += G::NT) {
-    const int i = idx / NC, z = idx % NC;
-    const double dz = node_coord(X.q2 + z - m, h, S.iz[i]);
-    S.ez[i][z] = (T)exp(-(dz * dz) * S.i2s[i]);
-    if constexpr (Vr::SEP) {
-      const double dx = node_coord(X.q0 + z - m, h, S.ix[i]);
-      const double dy = node_coord(X.q1 + z - m, h, S.iy[i]);
-      S.ex[i][z] = (T)exp(-(dx * dx) * S.i2s[i]);
-      S.ey[i][z] = (T)exp(-(dy * dy) * S.i2s[i]);
+  // ---- z-factor constants of every image; projection accumulators ----
+  for (int i = tid; i < Vr::NIMG; i += L::NT) {
+    double e0 = 0.0, r0 = 0.0, cq = 0.0;
+    if (i < nimg) {
+      const double u0 = node_coord(X.q2 - m, h, S.iz[i]);
+      const double is = S.i2s[i];
+      e0 = exp(-(u0 * u0) * is);
+      r0 = exp(-(2.0 * u0 * h + h * h) * is);
+      cq = exp(-2.0 * h * h * is);
     }
-  }
-  for (int i = tid; i < Vr::NIMG; i += G::NT) {
+    S.e0[i] = e0;
+    S.r0[i] = r0;
+    S.cq[i] = cq;
     S.pacc[0][i] = 0.0;
     S.pacc[1][i] = 0.0;
   }
-  for (int i = tid; i < Lay<Vr>::SIZE; i += G::NT) S.tl[i] = (T)0;
+  for (int i = tid; i < L::SIZE; i += L::NT) S.tl[i] = (T)0;
   if (tid == 0) S.nnear = 0;
+  __syncthreads();
 
   // ---- per-column chords of every image's spherical support ----
   X.nslot = 0;
 #pragma unroll
-  for (int s = 0; s < Vr::KC; ++s) X.sid[s] = 0;
-  if constexpr (!Vr::SEP) {
+  for (int s = 0; s < Vr::KC; ++s) X.sid[s] = 0u;
+  if constexpr (Vr::AREG) {
 #pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) X.sexy[s] = (T)0;
+    for (int s = 0; s < Vr::KC; ++s) X.a0[s] = 0.0;
   }
   if (X.active) {
     for (int i = 0; i < nimg; ++i) {
@@ -315,31 +360,28 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
       const double dxy2 = sq_sum2(dx, dy);
       const double rp2 = S.rp2[i];
       if (!(dxy2 < rp2)) continue;
-      int z0 = -1, z1 = -2;
+      unsigned bits = 0u;
       for (int z = 0; z < NC; ++z) {
         const double dz = node_coord(X.q2 + z - m, h, S.iz[i]);
-        if (sq_add(dxy2, dz) < rp2) {
-          if (z0 < 0) z0 = z;
-          z1 = z;
-        }
+        if (sq_add(dxy2, dz) < rp2) bits |= 0x80000000u >> z;
       }
-      if (z0 < 0) continue;
+      if (bits == 0u) continue;
       if (X.nslot >= Vr::KC) {
         atomicOr(err, SQ_ERR_SLOTS);
         continue;
       }
-      const int packed = i | (z0 << 8) | (z1 << 16);
-      T exy = (T)0;
-      if constexpr (!Vr::SEP) exy = (T)exp(-dxy2 * S.i2s[i]);
+      const unsigned word = bits | (unsigned)i;
 #pragma unroll
-      for (int s = 0; s < Vr::KC; ++s)
+      for (int s = 0; s < Vr::KC; ++s) {
         if (s == X.nslot) {
-          X.sid[s] = packed;
-          if constexpr (!Vr::SEP) X.sexy[s] = exy;
+          X.sid[s] = word;
+          if constexpr (Vr::AREG) X.a0[s] = exp(-dxy2 * S.i2s[i]) * S.e0[i];
         }
+      }
       ++X.nslot;
     }
   }
+  X.nsw = wave_max(X.nslot);
 
   // ---- diagonal: local potential (periodic) + stencil centre - shift ----
   const double cdiag = -0.5 / (h * h) * 3.0 * C.c2[0];
@@ -354,91 +396,110 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     }
     X.vd[z] = (T)(v + cdiag - shift);
   }
-  __syncthreads();
 }
 
-// One application of the nodal operator to the vector held in S.tl / cur:
+// Projector weights of one slot along the column: w(z) = a e(z)/e(0) on the
+// planes of the chord, zero elsewhere.  f(z, w) is called for every plane.
+template <int NC, class F>
+__device__ __forceinline__ void slot_sweep(unsigned mk, double a, double rr, double cq, F f) {
+#pragma unroll
+  for (int z = 0; z < NC; ++z) {
+    unsigned nm;
+    const bool on = __builtin_add_overflow(mk, mk, &nm);   // bit 31 - z
+    mk = nm;
+    f(z, on, a);
+    a *= rr;
+    rr *= cq;
+  }
+}
+
+// One application of the nodal operator to the vector held in registers
+// (cur) and mirrored in S.tl:
 //   io <- sc * ((H_q - shift) cur) - pm * io
-// (io holds the previous vector on entry and the new one on exit, mirrored
-// in S.tl).  par selects the projection accumulator (alternates per call).
+// io holds the previous vector on entry and the new one on exit (registers
+// only; the caller mirrors it).  par selects the projection accumulator; the
+// other one is cleared for the next step.  Ends after one block barrier.
 template <class Vr>
-__device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X,
+__device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
                                            const typename Vr::T (&cur)[Vr::NC],
                                            typename Vr::T (&io)[Vr::NC], const typename Vr::T* ck,
                                            double sc, typename Vr::T pm, int par) {
   using T = typename Vr::T;
+  using L = typename Vr::L;
   constexpr int NC = Vr::NC;
-  using G = Geo<NC>;
-  using Ly = Lay<Vr>;
-  const int nimg = S.nimg;
-  // keep the per-node slot data opaque so that nothing derived from it is
-  // hoisted across steps (register pressure)
+  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
+  const int nsw = X.nsw;
+  // keep the per-slot data opaque so that nothing derived from it is hoisted
+  // across steps (register pressure)
 #pragma unroll
   for (int s = 0; s < Vr::KC; ++s) opaque(X.sid[s]);
-  if constexpr (!Vr::SEP) {
+  if constexpr (Vr::AREG) {
 #pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) opaque(X.sexy[s]);
+    for (int s = 0; s < Vr::KC; ++s) opaque(X.a0[s]);
   }
-  const int base = Ly::at(X.cx, X.cy, 0);
-  // (1) projections <chi_I, cur> of every image
-  if (X.active) {
+  // (1) projections <chi_I, cur> of every image crossing this column
 #pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) {
-      if (s < X.nslot) {
-        const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
-        T part = (T)0;
-        for (int z = z0; z <= z1; ++z) part += S.ez[i][z] * S.tl[base + z * Ly::PL];
-        atomicAdd(&S.pacc[par][i], (double)(slot_exy<Vr>(S, X, s, i) * part));
-      }
+  for (int s = 0; s < Vr::KC; ++s) {
+    if (s < nsw) {
+      const unsigned mk = X.sid[s];
+      const int i = (int)(mk & IMASK);
+      T part = (T)0;
+      slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                     [&](int z, bool on, double a) { part += (on ? (T)a : (T)0) * cur[z]; });
+      if (s < X.nslot) atomicAdd(&S.pacc[par][i], (double)part);
     }
   }
-  __syncthreads();
   // (2) stencil + diagonal on the own column (x/y neighbours from LDS)
   if (X.active) {
     const int cx = X.cx, cy = X.cy;
+    const int base = L::at(cx, cy, 0);
     const T tsc = (T)sc;
 #pragma unroll
     for (int z = 0; z < NC; ++z) {
       T acc = X.vd[z] * cur[z];
-      const T* pc = S.tl + base + z * Ly::PL;
+      const T* pc = S.tl + base + z * L::PL;
 #pragma unroll
       for (int k = 1; k <= SQ_FDM; ++k) {
         T s = (T)0;
         if (z + k < NC) s += cur[z + k];
         if (z - k >= 0) s += cur[z - k];
-        if constexpr (Ly::PAD) {
-          s += (pc[k] + pc[-k]) + (pc[k * Ly::RS] + pc[-k * Ly::RS]);
+        if constexpr (L::RS > NC) {
+          s += (pc[k] + pc[-k]) + (pc[k * L::RS] + pc[-k * L::RS]);
         } else {
           if (cx + k < NC) s += pc[k];
           if (cx - k >= 0) s += pc[-k];
-          if (cy + k < NC) s += pc[k * Ly::RS];
-          if (cy - k >= 0) s += pc[-k * Ly::RS];
+          if (cy + k < NC) s += pc[k * L::RS];
+          if (cy - k >= 0) s += pc[-k * L::RS];
         }
         acc += ck[k] * s;
       }
       io[z] = tsc * acc - pm * io[z];
     }
   }
-  for (int i = threadIdx.x; i < nimg; i += G::NT) S.pacc[par ^ 1][i] = 0.0;
+  for (int i = threadIdx.x; i < Vr::NIMG; i += L::NT) S.pacc[par ^ 1][i] = 0.0;
   __syncthreads();
-  // (3) the projector terms, added through the LDS copy of the own column
-  if (X.active) {
+  // (3) the projector terms sc * gamma dV chi_I <chi_I, cur>
 #pragma unroll
-    for (int z = 0; z < NC; ++z) S.tl[base + z * Ly::PL] = io[z];
-    if (X.nslot > 0) {
-#pragma unroll
-      for (int s = 0; s < Vr::KC; ++s) {
-        if (s < X.nslot) {
-          const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
-          const T coef = (T)(sc * S.gdv[i] * S.pacc[par][i]) * slot_exy<Vr>(S, X, s, i);
-          for (int z = z0; z <= z1; ++z) S.tl[base + z * Ly::PL] += coef * S.ez[i][z];
-        }
-      }
-#pragma unroll
-      for (int z = 0; z < NC; ++z) io[z] = S.tl[base + z * Ly::PL];
+  for (int s = 0; s < Vr::KC; ++s) {
+    if (s < nsw) {
+      const unsigned mk = X.sid[s];
+      const int i = (int)(mk & IMASK);
+      const double coef = s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0;
+      slot_sweep<NC>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                     [&](int z, bool on, double a) { io[z] += on ? (T)a : (T)0; });
     }
   }
-  __syncthreads();
+}
+
+// Mirror the column into LDS (the caller places a barrier before it is read).
+template <class Vr>
+__device__ __forceinline__ void mirror(Smem<Vr>& S, const Ctx<Vr>& X, const typename Vr::T (&v)[Vr::NC]) {
+  using L = typename Vr::L;
+  if (X.active) {
+    const int base = L::at(X.cx, X.cy, 0);
+#pragma unroll
+    for (int z = 0; z < Vr::NC; ++z) S.tl[base + z * L::PL] = v[z];
+  }
 }
 
 template <class Vr>
@@ -446,13 +507,13 @@ __device__ __forceinline__ void load_unit(Smem<Vr>& S, Ctx<Vr>& X, typename Vr::
                                           typename Vr::T (&prv)[Vr::NC]) {
   using T = typename Vr::T;
   constexpr int NC = Vr::NC;
-  using G = Geo<NC>;
+  constexpr int m = NC / 2;
 #pragma unroll
   for (int z = 0; z < NC; ++z) {
-    cur[z] = (X.cx == G::MH && X.cy == G::MH && z == G::MH) ? (T)1 : (T)0;
+    cur[z] = (X.active && X.cx == m && X.cy == m && z == m) ? (T)1 : (T)0;
     prv[z] = (T)0;
-    if (X.active) S.tl[Lay<Vr>::at(X.cx, X.cy, z)] = cur[z];
   }
+  mirror<Vr>(S, X, cur);
   __syncthreads();
 }
 
@@ -464,6 +525,28 @@ __device__ __forceinline__ void stencil_coefs(const CellDev& C, T* ck) {
   for (int k = 1; k <= SQ_FDM; ++k) ck[k] = (T)(s * C.c2[k]);
 }
 
+// Block sums of two values; red is double-buffered by the caller (the next
+// use of the same buffer is separated by at least one more barrier).
+template <int NW>
+__device__ __forceinline__ void block_sum2_db(double& a, double& b, double* red) {
+  a = warp_sum(a);
+  b = warp_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+    red[w] = a;
+    red[NW + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    sa += red[i];
+    sb += red[NW + i];
+  }
+  a = sa;
+  b = sb;
+}
+
 // ---------------------------------------------------------------------------
 // Spectral bounds: K-step FP64 Lanczos on H_q from the unit vector w_q
 // (chi_q and zeta_q come from the extreme eigenvalues of H_q, Sec. IV)
@@ -471,23 +554,24 @@ __device__ __forceinline__ void stencil_coefs(const CellDev& C, T* ck) {
 // One Lanczos step with v_k in A (and S.tl), v_{k-1} in B on entry; on exit
 // v_{k+1} is in B (and S.tl) unless the recursion stopped.
 template <class Vr>
-__device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const double (&A)[Vr::NC],
-                                             double (&B)[Vr::NC], const double* ck, int k,
-                                             double& bprev, double& tol, double* lan) {
+__device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
+                                             const double (&A)[Vr::NC], double (&B)[Vr::NC],
+                                             const double* ck, int k, double& bprev, double& tol,
+                                             double* lan) {
   constexpr int NC = Vr::NC;
-  using G = Geo<NC>;
-  apply_step<Vr>(S, X, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
+  constexpr int NW = Vr::L::NW;
+  apply_step<Vr>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
   double a = 0.0, dum = 0.0;
 #pragma unroll
   for (int z = 0; z < NC; ++z) a += A[z] * B[z];
-  block_sum2<G::NW>(a, dum, S.red);
+  block_sum2_db<NW>(a, dum, S.red[0]);
   double b = 0.0;
 #pragma unroll
   for (int z = 0; z < NC; ++z) {
     B[z] -= a * A[z];
     b += B[z] * B[z];
   }
-  block_sum2<G::NW>(b, dum, S.red);
+  block_sum2_db<NW>(b, dum, S.red[1]);
   b = sqrt(b);
   if (threadIdx.x == 0) {
     lan[k] = a;
@@ -497,18 +581,16 @@ __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const doub
   if (b < tol) return false;
   const double ib = 1.0 / b;
 #pragma unroll
-  for (int z = 0; z < NC; ++z) {
-    B[z] *= ib;
-    if (X.active) S.tl[Lay<Vr>::at(X.cx, X.cy, z)] = B[z];
-  }
+  for (int z = 0; z < NC; ++z) B[z] *= ib;
+  mirror<Vr>(S, X, B);
   bprev = b;
   __syncthreads();
   return true;
 }
 
 template <class Vr>
-__global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_lanczos(PlanDev P, const long long* items,
-                                                              const int* item_cell) {
+__global__ void __launch_bounds__(Vr::L::NT) k_lanczos(PlanDev P, const long long* items,
+                                                        const int* item_cell) {
   static_assert(sizeof(typename Vr::T) == 8, "Lanczos runs in FP64");
   constexpr int NC = Vr::NC;
   __shared__ Smem<Vr> S;
@@ -526,10 +608,10 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_lanczos(PlanDev P, const lo
   double* lan = P.lan + g * (2 * SQ_KL_MAX);
   for (int k = 0; k < C.K; k += 2) {
     steps = k + 1;
-    if (!lanczos_step<Vr>(S, X, A, B, ck, k, bprev, tol, lan)) break;
+    if (!lanczos_step<Vr>(S, X, C, A, B, ck, k, bprev, tol, lan)) break;
     if (k + 1 >= C.K) break;
     steps = k + 2;
-    if (!lanczos_step<Vr>(S, X, B, A, ck, k + 1, bprev, tol, lan)) break;
+    if (!lanczos_step<Vr>(S, X, C, B, A, ck, k + 1, bprev, tol, lan)) break;
   }
   if (threadIdx.x == 0) P.lan_steps[g] = steps;
 }
@@ -541,11 +623,11 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_lanczos(PlanDev P, const lo
 // (Hhat_q is symmetric, T_{a+b} + T_{|a-b|} = 2 T_a T_b).
 // ---------------------------------------------------------------------------
 template <class Vr>
-__global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_moments(PlanDev P, const long long* items,
-                                                              const int* item_cell) {
+__global__ void __launch_bounds__(Vr::L::NT) k_moments(PlanDev P, const long long* items,
+                                                        const int* item_cell) {
   using T = typename Vr::T;
   constexpr int NC = Vr::NC;
-  using G = Geo<NC>;
+  constexpr int NW = Vr::L::NW;
   __shared__ Smem<Vr> S;
   const long long g = items[blockIdx.x];
   const CellDev& C = P.cells[item_cell[blockIdx.x]];
@@ -565,7 +647,7 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_moments(PlanDev P, const lo
   if (threadIdx.x == 0) mom[0] = 1.0;
   // t^{k+1} from t^k (cur) and t^{k-1} (io); then rho^{2k+1}, rho^{2k+2}
   auto step = [&](const T (&cur)[NC], T (&io)[NC], int k) {
-    apply_step<Vr>(S, X, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, k == 0 ? (T)0 : (T)1,
+    apply_step<Vr>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, k == 0 ? (T)0 : (T)1,
                    k & 1);
     double sq = 0.0, cr = 0.0;
 #pragma unroll
@@ -574,7 +656,8 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_moments(PlanDev P, const lo
       sq += a * a;
       cr += a * b;
     }
-    block_sum2<G::NW>(sq, cr, S.red);
+    mirror<Vr>(S, X, io);
+    block_sum2_db<NW>(sq, cr, S.red[k & 1]);
     if (k == 0) rho1 = cr;
     const int j1 = 2 * k + 1, j2 = 2 * k + 2;
     const double r1 = (k == 0) ? cr : 2.0 * cr - rho1;
@@ -606,29 +689,26 @@ __device__ __forceinline__ void grad_xy_round(Smem<Vr>& S, Ctx<Vr>& X,
                                               const double* w) {
   constexpr int NC = Vr::NC;
   using T = typename Vr::T;
-  using Ly = Lay<Vr>;
-  const int base = Ly::at(X.cx, X.cy, 0);
-  if (X.active) {
-#pragma unroll
-    for (int z = 0; z < NC; ++z) S.tl[base + z * Ly::PL] = part[z];
-  }
+  using L = typename Vr::L;
+  const int base = L::at(X.cx, X.cy, 0);
+  mirror<Vr>(S, X, part);
   __syncthreads();
   if (X.active) {
     const int cx = X.cx, cy = X.cy;
 #pragma unroll
     for (int z = 0; z < NC; ++z) {
-      const T* pc = S.tl + base + z * Ly::PL;
+      const T* pc = S.tl + base + z * L::PL;
       double ax = 0.0, ay = 0.0;
 #pragma unroll
       for (int k = 1; k <= SQ_FDM; ++k) {
-        if constexpr (Ly::PAD) {
+        if constexpr (L::RS > NC) {
           ax += w[k] * ((double)pc[k] - (double)pc[-k]);
-          ay += w[k] * ((double)pc[k * Ly::RS] - (double)pc[-k * Ly::RS]);
+          ay += w[k] * ((double)pc[k * L::RS] - (double)pc[-k * L::RS]);
         } else {
           if (cx + k < NC) ax += w[k] * (double)pc[k];
           if (cx - k >= 0) ax -= w[k] * (double)pc[-k];
-          if (cy + k < NC) ay += w[k] * (double)pc[k * Ly::RS];
-          if (cy - k >= 0) ay -= w[k] * (double)pc[-k * Ly::RS];
+          if (cy + k < NC) ay += w[k] * (double)pc[k * L::RS];
+          if (cy - k >= 0) ay -= w[k] * (double)pc[-k * L::RS];
         }
       }
       gx[z] += ax;
@@ -639,12 +719,14 @@ __device__ __forceinline__ void grad_xy_round(Smem<Vr>& S, Ctx<Vr>& X,
 }
 
 template <class Vr>
-__global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const long long* items,
-                                                             const int* item_cell) {
+__global__ void __launch_bounds__(Vr::L::NT) k_stress(PlanDev P, const long long* items,
+                                                       const int* item_cell) {
   using T = typename Vr::T;
+  using L = typename Vr::L;
   constexpr int NC = Vr::NC;
-  using G = Geo<NC>;
-  constexpr int m = G::MH;
+  constexpr int NC2 = NC * NC;
+  constexpr int m = L::MH;
+  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
   __shared__ Smem<Vr> S;
   const long long g = items[blockIdx.x];
   const CellDev& C = P.cells[item_cell[blockIdx.x]];
@@ -663,11 +745,13 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const lon
   for (int z = 0; z < NC; ++z) d[z] = c0h * (double)A[z];
   const int npl = C.npl;
   auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
-    apply_step<Vr>(S, X, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta, j == 0 ? (T)0 : (T)1,
+    apply_step<Vr>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta, j == 0 ? (T)0 : (T)1,
                    j & 1);
     const double cj = coef[j + 1];
 #pragma unroll
     for (int z = 0; z < NC; ++z) d[z] += cj * (double)io[z];
+    mirror<Vr>(S, X, io);
+    __syncthreads();
   };
   for (int j = 0; j < npl; j += 2) {
     step(A, B, j);
@@ -711,17 +795,17 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const lon
 
   // ---- kinetic functional from the plane z = m and the centre column ----
   double* plane = reinterpret_cast<double*>(S.tl);   // 3 * NC2 + 3 * NC doubles
-  static_assert(sizeof(T) * Lay<Vr>::SIZE >= sizeof(double) * (3 * G::NC2 + 3 * NC), "plane");
+  static_assert(sizeof(T) * L::SIZE >= sizeof(double) * (3 * NC2 + 3 * NC), "plane");
   if (X.active) {
     plane[X.col] = gx[m];
-    plane[G::NC2 + X.col] = gy[m];
-    plane[2 * G::NC2 + X.col] = gz[m];
+    plane[NC2 + X.col] = gy[m];
+    plane[2 * NC2 + X.col] = gz[m];
     if (X.cx == m && X.cy == m) {
 #pragma unroll
       for (int z = 0; z < NC; ++z) {
-        plane[3 * G::NC2 + z] = gx[z];
-        plane[3 * G::NC2 + NC + z] = gy[z];
-        plane[3 * G::NC2 + 2 * NC + z] = gz[z];
+        plane[3 * NC2 + z] = gx[z];
+        plane[3 * NC2 + NC + z] = gy[z];
+        plane[3 * NC2 + 2 * NC + z] = gz[z];
       }
     }
   }
@@ -731,8 +815,9 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const lon
 #pragma unroll
     for (int s = 0; s < Vr::KC; ++s) {
       if (s < X.nslot) {
-        const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
-        if (z0 <= m && m <= z1) {
+        const unsigned mk = X.sid[s];
+        const int i = (int)(mk & IMASK);
+        if (mk & (0x80000000u >> m)) {
           if (nn < Vr::NEAR) {
             S.near_img[nn] = i;
             const double dx = node_coord(X.q0, C.h, S.ix[i]);
@@ -748,15 +833,15 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const lon
     }
     S.nnear = nn < Vr::NEAR ? nn : Vr::NEAR;
   }
-  for (int i = threadIdx.x; i < Vr::NEAR * 10; i += G::NT) (&S.nsum[0][0])[i] = 0.0;
+  for (int i = threadIdx.x; i < Vr::NEAR * 10; i += L::NT) (&S.nsum[0][0])[i] = 0.0;
   __syncthreads();
 
   double* rec = P.rec + g * SQ_REC;
   if (threadIdx.x == 0) {
     const double* px = plane;
-    const double* py = plane + G::NC2;
-    const double* pz = plane + 2 * G::NC2;
-    const double* cxg = plane + 3 * G::NC2;
+    const double* py = plane + NC2;
+    const double* pz = plane + 2 * NC2;
+    const double* cxg = plane + 3 * NC2;
     // (grad_a G_b)(c) = (1/h) sum_k w_k (G_b(c + k e_a) - G_b(c - k e_a))
     for (int b = 0; b < 3; ++b) {
       const double* pb = b == 0 ? px : (b == 1 ? py : pz);
@@ -782,30 +867,29 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const lon
 #pragma unroll
     for (int s = 0; s < Vr::KC; ++s) {
       if (s < X.nslot) {
-        const int i = X.sid[s] & 0xff, z0 = (X.sid[s] >> 8) & 0xff, z1 = (X.sid[s] >> 16) & 0xff;
+        const unsigned mk = X.sid[s];
+        const int i = (int)(mk & IMASK);
         int nidx = -1;
         for (int n = 0; n < nnear; ++n)
           if (S.near_img[n] == i) nidx = n;
         if (nidx >= 0) {
-          const double exy = (double)slot_exy<Vr>(S, X, s, i);
           const double rx = xc - S.ix[i], ry = yc - S.iy[i];
           double acc[10];
 #pragma unroll
           for (int t = 0; t < 10; ++t) acc[t] = 0.0;
+          slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                         [&](int z, bool on, double chiv) {
+                           if (on) {
+                             const double rz = (double)(X.q2 + z - m) * C.h - S.iz[i];
+                             acc[0] += chiv * d[z];
+                             const double ga[3] = {gx[z], gy[z], gz[z]};
+                             const double rb[3] = {rx, ry, rz};
 #pragma unroll
-          for (int z = 0; z < NC; ++z) {
-            if (z >= z0 && z <= z1) {
-              const double chiv = exy * (double)S.ez[i][z];
-              const double rz = (double)(X.q2 + z - m) * C.h - S.iz[i];
-              acc[0] += chiv * d[z];
-              const double ga[3] = {gx[z], gy[z], gz[z]};
-              const double rb[3] = {rx, ry, rz};
+                             for (int a = 0; a < 3; ++a)
 #pragma unroll
-              for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += chiv * rb[b] * ga[a];
-            }
-          }
+                               for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += chiv * rb[b] * ga[a];
+                           }
+                         });
 #pragma unroll
           for (int t = 0; t < 10; ++t) atomicAdd(&S.nsum[nidx][t], acc[t]);
         }
@@ -830,13 +914,13 @@ __global__ void __launch_bounds__(Geo<Vr::NC>::NT) k_stress(PlanDev P, const lon
 // ---------------------------------------------------------------------------
 // Capacity census (set-up time): per node the number of atom images reaching
 // its cube, the largest number crossing one z-column, and the number whose
-// projector is nonzero at the node.  Maxima per cell go to stats[3 * cell].
+// projector is nonzero at the node.  Maxima per cell go to stats[4 * cell].
 // ---------------------------------------------------------------------------
 template <int NC>
-__global__ void __launch_bounds__(Geo<NC>::NT) k_census(PlanDev P, const long long* items,
-                                                         const int* item_cell, int* stats,
-                                                         long long* pair_total) {
-  using G = Geo<NC>;
+__global__ void __launch_bounds__(sq_threads(NC)) k_census(PlanDev P, const long long* items,
+                                                            const int* item_cell, int* stats,
+                                                            long long* pair_total) {
+  constexpr int NT = sq_threads(NC);
   constexpr int CAP = 512;
   __shared__ double sx[CAP], sy[CAP], sz[CAP], srp2[CAP];
   __shared__ int wcnt[16], cnt, colmax, nnear;
@@ -845,7 +929,7 @@ __global__ void __launch_bounds__(Geo<NC>::NT) k_census(PlanDev P, const long lo
   const int ci = item_cell[blockIdx.x];
   const CellDev& C = P.cells[ci];
   const long long q = g - C.node_base;
-  const int m = G::MH;
+  const int m = NC / 2;
   const long long q0 = q % C.n[0], q1 = (q / C.n[0]) % C.n[1], q2 = q / ((long long)C.n[0] * C.n[1]);
   auto store = [&](int pos, int I) {
     sx[pos] = C.img[4 * I];
@@ -854,7 +938,7 @@ __global__ void __launch_bounds__(Geo<NC>::NT) k_census(PlanDev P, const long lo
     const double rp = C.sp[(int)C.img[4 * I + 3]].p_rc;
     srp2[pos] = rp * rp;
   };
-  const int found = gather_images<G::NT, G::NW, CAP>(C, q0, q1, q2, m, &cnt, wcnt, store, P.err);
+  const int found = gather_images<NT, NT / 64, CAP>(C, q0, q1, q2, m, &cnt, wcnt, store, P.err);
   const int nimg = found < CAP ? found : CAP;
   if (threadIdx.x == 0) {
     colmax = 0;
@@ -863,7 +947,7 @@ __global__ void __launch_bounds__(Geo<NC>::NT) k_census(PlanDev P, const long lo
   }
   __syncthreads();
   const int tid = threadIdx.x;
-  if (tid < G::NC2) {
+  if (tid < NC * NC) {
     const int cx = tid % NC, cy = tid / NC;
     int count = 0, near = 0, pairs = 0;
     for (int i = 0; i < nimg; ++i) {
@@ -1293,9 +1377,11 @@ __global__ void __launch_bounds__(256) k_vloc(const CellDev* cell, double* out) 
 SQ_NC_LIST(SQ_DECL_NC)
 
 // Largest slot capacity per precision and width (0: unsupported).
-__host__ __device__ constexpr int sq_kc_max(bool fp64, int nc) {
-  return fp64 ? (nc <= 21 ? 48 : 24) : 48;
-}
+__host__ __device__ constexpr int sq_kc_max(bool, int) { return 48; }
+
+// Largest number of atom images one cube may see (the image index shares a
+// 32-bit slot word with the chord bits of the NC planes).
+__host__ __device__ constexpr int sq_img_max(int nc) { return (1 << (32 - nc)) < 160 ? (1 << (32 - nc)) : 160; }
 
 #ifdef SQ_ONE_NC
 #define SQ_CAT2(a, b) a##b
@@ -1311,7 +1397,7 @@ enum Fam { FAM_LAN, FAM_MOM, FAM_STR };
 template <class Vr, int F>
 hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, long long n,
                       hipStream_t s) {
-  const dim3 grid((unsigned)n), block(Geo<Vr::NC>::NT);
+  const dim3 grid((unsigned)n), block(Vr::L::NT);
   if constexpr (F == FAM_LAN)
     hipLaunchKernelGGL(k_lanczos<Vr>, grid, block, 0, s, P, items, ic);
   else if constexpr (F == FAM_MOM)
@@ -1324,11 +1410,9 @@ hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, l
 template <int F>
 hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
                        hipStream_t s) {
-  if (kc <= 16) return launch_var<Var<double, SQN, 16, false>, F>(P, items, ic, n, s);
-  if (kc <= 24) return launch_var<Var<double, SQN, 24, false>, F>(P, items, ic, n, s);
-  if constexpr (SQN <= 21) {
-    if (kc <= 48) return launch_var<Var<double, SQN, 48, true>, F>(P, items, ic, n, s);
-  }
+  if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F>(P, items, ic, n, s);
+  if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F>(P, items, ic, n, s);
+  if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F>(P, items, ic, n, s);
   return hipErrorInvalidValue;
 }
 
@@ -1337,7 +1421,7 @@ hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const i
                        hipStream_t s) {
   if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F>(P, items, ic, n, s);
   if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F>(P, items, ic, n, s);
-  if (kc <= 48) return launch_var<Var<float, SQN, 48, true>, F>(P, items, ic, n, s);
+  if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F>(P, items, ic, n, s);
   return hipErrorInvalidValue;
 }
 }  // namespace
@@ -1364,7 +1448,7 @@ hipError_t SQ_CAT(sq_launch_stress_, SQ_ONE_NC)(bool fp64, int kc, const PlanDev
 hipError_t SQ_CAT(sq_launch_census_, SQ_ONE_NC)(const PlanDev& P, const long long* items,
                                                const int* ic, long long n, int* stats,
                                                long long* pairs, hipStream_t s) {
-  hipLaunchKernelGGL(k_census<SQN>, dim3((unsigned)n), dim3(Geo<SQN>::NT), 0, s, P, items, ic, stats,
+  hipLaunchKernelGGL(k_census<SQN>, dim3((unsigned)n), dim3(sq_threads(SQN)), 0, s, P, items, ic, stats,
                      pairs);
   return hipGetLastError();
 }
@@ -1379,6 +1463,8 @@ bool sq_nc_supported(int nc) {
 }
 
 int sq_kc_limit(bool fp64, int nc) { return sq_kc_max(fp64, nc); }
+
+int sq_img_limit(int nc) { return sq_img_max(nc); }
 
 hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
                              const int* item_cell, long long nitems, hipStream_t s) {
