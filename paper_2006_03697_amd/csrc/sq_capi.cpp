@@ -460,7 +460,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   P.coef = (double*)A(sizeof(double) * P.mstride * N);
   P.rec = (double*)A(sizeof(double) * SQ_REC * N);
   P.nq = (double*)A(sizeof(double) * N);
-  P.mus = (double*)A(sizeof(double) * 8 * n_cells);
+  P.mus = (double*)A(sizeof(double) * SQ_MU_STRIDE * n_cells);
   P.sums = (double*)A(sizeof(double) * (SQ_REC + 4) * n_cells);
   P.err = (unsigned*)A(sizeof(unsigned) * 4);
   p->d_cells = (CellDev*)A(sizeof(CellDev) * n_cells);
@@ -682,10 +682,11 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
   if (st != SQ_OK) return st;
   st = check_errors(p);
   if (st != SQ_OK) return st;
-  // Fermi level: bisection entirely on the device, checked every 16 steps
-  std::vector<double> mus(8 * p->cells.size());
-  for (int it = 0; it < 208 && st == SQ_OK; it += 16) {
-    for (int k = 0; k < 16 && st == SQ_OK; ++k) {
+  // Fermi level: bracketed root search entirely on the device; the host
+  // checks for completion after 10 evaluations, then every 4
+  std::vector<double> mus(SQ_MU_STRIDE * p->cells.size());
+  for (int it = 0, blk = 10; it < 210 && st == SQ_OK; it += blk, blk = 4) {
+    for (int k = 0; k < blk && st == SQ_OK; ++k) {
       st = check_hip(p, sq_launch_mu_eval(p->P, S->items, S->item_cell, S->nall, s), "mu eval");
       if (st == SQ_OK) st = check_hip(p, sq_launch_mu_step(p->P, S->d_cells, nc, s), "mu step");
     }
@@ -694,15 +695,15 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
                                      hipMemcpyDeviceToHost, s), "mu copy");
     if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "mu sync");
     bool done = true;
-    for (int ci : S->cells) done = done && mus[8 * ci + MU_DONE] != 0.0;
+    for (int ci : S->cells) done = done && mus[SQ_MU_STRIDE * ci + MU_DONE] != 0.0;
     if (done) break;
   }
   if (st != SQ_OK) return st;
   for (int ci : S->cells) {
-    if (mus[8 * ci + MU_DONE] == 2.0)
+    if (mus[SQ_MU_STRIDE * ci + MU_DONE] == 2.0)
       return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": N_e not bracketed");
-    if (mus[8 * ci + MU_DONE] == 0.0)
-      return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": bisection did not finish");
+    if (mus[SQ_MU_STRIDE * ci + MU_DONE] == 0.0)
+      return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": Fermi-level search did not finish");
   }
   phase_end(p, PH_MU);
   phase_begin(p, PH_COEFFS);
@@ -725,7 +726,7 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
   }
   if (mu) {
     for (size_t i = 0; i < S->cells.size(); ++i) {
-      const double v = mus[8 * S->cells[i] + MU_VAL];
+      const double v = mus[SQ_MU_STRIDE * S->cells[i] + MU_VAL];
       if (p->opt.outputs_on_device)
         st = check_hip(p, hipMemcpyAsync(mu + i, &v, sizeof(double), hipMemcpyHostToDevice, s), "mu");
       else

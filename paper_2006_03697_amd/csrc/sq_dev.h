@@ -1,5 +1,5 @@
 // sq_dev.h -- device-side data layout shared by the host plan (sq_capi.cpp)
-// and the gfx950 kernels (sq_kernels.hip).
+// and the gfx950 kernels (sq_recur.hip, sq_misc.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -60,18 +60,23 @@ struct PlanDev {
   int mstride;
 };
 
-// mus layout
-#define MU_LO 0
+// mus layout: SQ_MU_STRIDE doubles per cell
+#define SQ_MU_STRIDE 16
+#define MU_LO 0      // bracket with N(lo) < N_e < N(hi)
 #define MU_HI 1
-#define MU_MID 2
-#define MU_VAL 3
-#define MU_DONE 4
+#define MU_MID 2     // trial Fermi level of the next evaluation
+#define MU_VAL 3     // result
+#define MU_DONE 4    // 0 running, 1 done, 2 not bracketed
 #define MU_IT 5
 #define MU_PHASE 6
-#define MU_N 7
+#define MU_N 7       // last electron count
+#define MU_FLO 8     // N(lo) - N_e (Illinois-scaled)
+#define MU_FHI 9     // N(hi) - N_e (Illinois-scaled)
+#define MU_SIDE 10   // end point replaced last: -1 lo, +1 hi
+#define MU_WID 11    // bracket width at the last progress check
 
 extern "C++" {
-// launchers (sq_kernels.hip)
+// launchers (sq_recur.hip per cube width, sq_misc.hip)
 hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s);
 hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
                              const int* item_cell, long long nitems, hipStream_t s);

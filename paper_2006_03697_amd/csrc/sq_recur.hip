@@ -1,5 +1,7 @@
-// sq_kernels.hip -- gfx950 kernels of the infinite-cell Clenshaw-Curtis SQ
-// hot path (arXiv 2006.03697, Sec. IV and App. A).
+// sq_recur.hip -- gfx950 recurrence kernels of the infinite-cell
+// Clenshaw-Curtis SQ hot path (arXiv 2006.03697, Sec. IV and App. A):
+// spectral-bound Lanczos, Chebyshev moments, the stress pass and the
+// capacity census.  Compiled once per cube width NC (SQ_ONE_NC).
 //
 // One workgroup owns one node q and its cube (region of influence) of
 // NC^3 finite-difference nodes.  Thread (cx, cy) owns the z-column of the
@@ -7,80 +9,17 @@
 // diagonal of H_q on that column live in its registers; the current vector
 // is mirrored in LDS so that x/y neighbours of the 12th-order stencil are
 // LDS reads and z neighbours are register reads.  Atom-image projectors are
-// evaluated from separable Gaussian factors: per image a table of the
-// z factor (LDS) and, per (column, image), the xy factor and the z chord of
-// the spherical support (registers, computed once per node).
-#include "sq_dev.h"
+// separable Gaussians cut off at a sphere: per (column, image) the chord of
+// the sphere on the column as a bit mask and the projector value at the
+// column's first plane (registers, computed once per node); along the column
+// the Gaussian factor follows from a two-multiply recurrence.
+#include "sq_devfn.h"
 
-#include <math.h>
-
-namespace {
-
-// ---------------------------------------------------------------------------
-// geometry helpers: the same IEEE operations as the oracle, no contraction
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double node_coord(long long i, double h, double R) {
-#pragma clang fp contract(off)
-  return (double)i * h - R;
-}
-
-__device__ __forceinline__ double sq_sum2(double a, double b) {
-#pragma clang fp contract(off)
-  return a * a + b * b;
-}
-
-__device__ __forceinline__ double sq_add(double s, double c) {
-#pragma clang fp contract(off)
-  return s + c * c;
-}
-
-__device__ __forceinline__ long long wrapll(long long i, long long n) {
-  long long r = i % n;
-  return r < 0 ? r + n : r;
-}
-
-// Make a register value opaque to the optimiser (no hoisting of values
-// derived from it); 64-bit values go through their two 32-bit halves.
-#ifdef SQ_NO_OPAQUE
-template <typename U>
-__device__ __forceinline__ void opaque(U&) {}
-#else
-__device__ __forceinline__ void opaque(int& x) { asm volatile("" : "+v"(x)); }
-__device__ __forceinline__ void opaque(unsigned& x) { asm volatile("" : "+v"(x)); }
-__device__ __forceinline__ void opaque(float& x) {
-  unsigned u = __float_as_uint(x);
-  asm volatile("" : "+v"(u));
-  x = __uint_as_float(u);
-}
-__device__ __forceinline__ void opaque(double& x) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-  unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
-  asm volatile("" : "+v"(lo), "+v"(hi));
-  x = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
+#ifndef SQ_ONE_NC
+#error "sq_recur.hip is compiled once per cube width: define SQ_ONE_NC"
 #endif
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ double warp_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-__device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
-  double t = ceil(8.0 * zeta / kT);
-  double tgt = fmax((double)(4 * (npl + 2)), t);
-  int M = 1;
-  while ((double)M < tgt) M <<= 1;
-  return M;
-}
-
+namespace {
 // ---------------------------------------------------------------------------
 // Cube layout in LDS and the thread <-> z-column map
 //
@@ -979,411 +918,8 @@ __global__ void __launch_bounds__(sq_threads(NC)) k_census(PlanDev P, const long
   }
 }
 
-
-// Number of eigenvalues of the tridiagonal (a, b) below x (Sturm count).
-__device__ int sturm_count(const double* a, const double* b, int n, double x) {
-  int c = 0;
-  double d = a[0] - x;
-  if (d < 0) ++c;
-  for (int i = 1; i < n; ++i) {
-    if (d == 0.0) d = -1e-300;
-    d = a[i] - x - b[i - 1] * b[i - 1] / d;
-    if (d < 0) ++c;
-  }
-  return c;
-}
-
-// Square of the last component of the unit eigenvector of eigenvalue x:
-// p_{n-1}(x) / p_n'(x) with p_k the characteristic polynomials of the
-// leading k x k blocks (three-term recurrence, rescaled against overflow).
-__device__ double last_component_sq(const double* a, const double* b, int n, double x) {
-  double pm2 = 1.0, pm1 = x - a[0];
-  double dm2 = 0.0, dm1 = 1.0;
-  for (int k = 1; k < n; ++k) {
-    const double bb = b[k - 1] * b[k - 1];
-    const double p = (x - a[k]) * pm1 - bb * pm2;
-    const double d = pm1 + (x - a[k]) * dm1 - bb * dm2;
-    pm2 = pm1;
-    pm1 = p;
-    dm2 = dm1;
-    dm1 = d;
-    const double mx = fmax(fabs(pm1), fabs(dm1));
-    if (mx > 1e150) {
-      pm1 *= 1e-150;
-      pm2 *= 1e-150;
-      dm1 *= 1e-150;
-      dm2 *= 1e-150;
-    }
-  }
-  // p_{n-1} = pm2, p_n' = dm1
-  return pm2 / dm1;
-}
-
-__global__ void k_bounds(PlanDev P, const long long* items, const int* item_cell, long long nitems) {
-  const long long it = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (it >= nitems) return;
-  const long long g = items[it];
-  const double* lan = P.lan + g * (2 * SQ_KL_MAX);
-  const int n = P.lan_steps[g];
-  const double* a = lan;
-  const double* b = lan + SQ_KL_MAX;
-  double lo, hi;
-  if (n <= 1) {
-    lo = a[0] - b[0];
-    hi = a[0] + b[0];
-  } else {
-    // Gershgorin interval
-    double glo = a[0] - fabs(b[0]), ghi = a[0] + fabs(b[0]);
-    for (int i = 1; i < n; ++i) {
-      const double r = fabs(b[i - 1]) + (i < n - 1 ? fabs(b[i]) : 0.0);
-      glo = fmin(glo, a[i] - r);
-      ghi = fmax(ghi, a[i] + r);
-    }
-    const double pad = 1e-12 * fmax(fabs(glo), fabs(ghi)) + 1e-300;
-    glo -= pad;
-    ghi += pad;
-    // smallest eigenvalue: count(x) goes 0 -> 1
-    double l = glo, u = ghi;
-    for (int i = 0; i < 200; ++i) {
-      const double mid = 0.5 * (l + u);
-      if (mid <= l || mid >= u) break;
-      if (sturm_count(a, b, n, mid) >= 1) u = mid; else l = mid;
-    }
-    const double tmin = 0.5 * (l + u);
-    // largest eigenvalue: count(x) goes n-1 -> n
-    l = glo;
-    u = ghi;
-    for (int i = 0; i < 200; ++i) {
-      const double mid = 0.5 * (l + u);
-      if (mid <= l || mid >= u) break;
-      if (sturm_count(a, b, n, mid) >= n) u = mid; else l = mid;
-    }
-    const double tmax = 0.5 * (l + u);
-    const double smin = sqrt(fabs(last_component_sq(a, b, n, tmin)));
-    const double smax = sqrt(fabs(last_component_sq(a, b, n, tmax)));
-    lo = tmin - b[n - 1] * smin;
-    hi = tmax + b[n - 1] * smax;
-  }
-  double* bd = P.bnd + 4 * g;
-  bd[0] = lo;
-  bd[1] = hi;
-  bd[2] = 0.5 * (hi + lo);
-  bd[3] = 0.5 * (hi - lo);
-}
-
-// ---------------------------------------------------------------------------
-// Clenshaw-Curtis coefficients and the Fermi level (Sec. IV, App. A)
-//
-// c_j = (2/M) sum_k g(cos th_k) cos(j th_k), th_k = pi (k + 1/2) / M.  Off a
-// window of +-40 kT around mu the FP64 occupation is exactly 0 or 1, so the
-// sum splits into a closed-form tail  sum_{k >= a} cos(j th_k) =
-//   sin((M - a) j pi / 2M) cos((a + M) j pi / 2M) / sin(j pi / 2M)
-// and the window points.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double tail_cos_sum(int j, int a, int M) {
-  if (a >= M) return 0.0;
-  if (j == 0) return (double)(M - a);
-  const double tm = 2.0 * (double)M;
-  return sinpi((double)(M - a) * j / tm) * cospi((double)(a + M) * j / tm) / sinpi((double)j / tm);
-}
-
-struct Window {
-  int M, kb, ka;
-  double muh, sigh;
-};
-
-__device__ __forceinline__ Window fermi_window(double mu, double chi, double zeta, double kT, int npl) {
-  Window W;
-  W.M = quad_points(zeta, kT, npl);
-  W.muh = (mu - chi) / zeta;
-  W.sigh = kT / zeta;
-  const double xb = W.muh + 40.0 * W.sigh;   // above: occupation 0
-  const double xa = W.muh - 40.0 * W.sigh;   // below: occupation 1
-  const double M = (double)W.M;
-  // x_k <= xb  <=>  k >= M acos(xb)/pi - 1/2
-  int kb = xb >= 1.0 ? 0 : (xb <= -1.0 ? W.M : (int)floor(M * acos(xb) / M_PI - 0.5) - 1);
-  int ka = xa <= -1.0 ? W.M - 1 : (xa >= 1.0 ? -1 : (int)ceil(M * acos(xa) / M_PI - 0.5) + 1);
-  W.kb = kb < 0 ? 0 : (kb > W.M ? W.M : kb);
-  W.ka = ka > W.M - 1 ? W.M - 1 : (ka < -1 ? -1 : ka);
-  return W;
-}
-
-__device__ __forceinline__ double occupation(double x, const Window& W) {
-  return 0.5 * (1.0 - tanh((x - W.muh) / (2.0 * W.sigh)));
-}
-
-// One wave per node: N_q(mu) = sum'_j c_q^j(mu) rho_q^j.
-__global__ void __launch_bounds__(256) k_mu_eval(PlanDev P, const long long* items,
-                                                 const int* item_cell, long long nitems) {
-  __shared__ double smom[4][260];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long it = blockIdx.x * 4ll + wv;
-  if (it >= nitems) return;   // whole wave leaves; only wave-level syncs below
-  const long long g = items[it];
-  const int ci = item_cell[it];
-  const double* mus = P.mus + 8 * ci;
-  if (mus[MU_DONE] != 0.0) return;
-  const CellDev& C = P.cells[ci];
-  const int npl = C.npl;
-  const double* mom = P.mom + g * P.mstride;
-  for (int j = lane; j <= npl; j += 64) smom[wv][j] = mom[j];
-  wave_sync();
-  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
-  const Window W = fermi_window(mus[MU_MID], chi, zeta, C.kT, npl);
-  double acc = 0.0;
-  // occupied tail: sum'_j rho^j S_j(ka + 1)
-  for (int j = lane; j <= npl; j += 64) {
-    const double r = j == 0 ? 0.5 * smom[wv][0] : smom[wv][j];
-    acc += r * tail_cos_sum(j, W.ka + 1, W.M);
-  }
-  // window points: g_k * sum'_j rho^j T_j(x_k) (Clenshaw)
-  for (int k = W.kb + lane; k <= W.ka; k += 64) {
-    const double x = cospi(((double)k + 0.5) / (double)W.M);
-    const double occ = occupation(x, W);
-    double b1 = 0.0, b2 = 0.0;
-    for (int j = npl; j >= 1; --j) {
-      const double b0 = smom[wv][j] + 2.0 * x * b1 - b2;
-      b2 = b1;
-      b1 = b0;
-    }
-    const double R = 0.5 * smom[wv][0] + x * b1 - b2;
-    acc += occ * R;
-  }
-  acc = warp_sum(acc);
-  if (lane == 0) P.nq[g] = (2.0 / (double)W.M) * acc;
-}
-
-// One wave per node: c_j, d_j at the final mu, rho_q and e_q.
-__global__ void __launch_bounds__(256) k_coeffs(PlanDev P, const long long* items,
-                                                const int* item_cell, long long nitems) {
-  __shared__ double sg[4][256];
-  __shared__ double sc[4][264];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long it = blockIdx.x * 4ll + wv;
-  const bool live = it < nitems;
-  const long long g = live ? items[it] : 0;
-  const int ci = live ? item_cell[it] : 0;
-  const CellDev& C = P.cells[ci];
-  const int npl = C.npl;
-  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
-  const double mu = P.mus[8 * ci + MU_VAL];
-  const Window W = fermi_window(mu, chi, zeta, C.kT, npl);
-  const double* mom = P.mom + g * P.mstride;
-  // per lane: coefficients j = lane + 64 r
-  double cacc[5] = {0, 0, 0, 0, 0};
-  for (int r = 0; r < 5; ++r) {
-    const int j = lane + 64 * r;
-    if (j <= npl + 1) cacc[r] = tail_cos_sum(j, W.ka + 1, W.M);
-  }
-  for (int base = W.kb; base <= W.ka; base += 256) {
-    // occupations of 256 window points into LDS
-    for (int t = lane; t < 256; t += 64) {
-      const int k = base + t;
-      double o = 0.0;
-      if (k <= W.ka) o = occupation(cospi(((double)k + 0.5) / (double)W.M), W);
-      sg[wv][t] = o;
-    }
-    wave_sync();
-    const int kend = min(base + 256, W.ka + 1);
-    for (int r = 0; r < 5; ++r) {
-      const int j = lane + 64 * r;
-      if (j > npl + 1) break;
-      double a = 0.0;
-      for (int k = base; k < kend; ++k) a += sg[wv][k - base] * cospi((double)j * ((double)k + 0.5) / (double)W.M);
-      cacc[r] += a;
-    }
-    wave_sync();
-  }
-  const double f = 2.0 / (double)W.M;
-  for (int r = 0; r < 5; ++r) {
-    const int j = lane + 64 * r;
-    if (j <= npl + 1) sc[wv][j] = f * cacc[r];
-  }
-  wave_sync();
-  if (!live) return;
-  double rs = 0.0, es = 0.0;
-  for (int j = lane; j <= npl; j += 64) {
-    const double cj = sc[wv][j];
-    const double dj = 0.5 * (sc[wv][j + 1] + sc[wv][j == 0 ? 1 : j - 1]);
-    const double wgt = j == 0 ? 0.5 : 1.0;
-    rs += wgt * cj * mom[j];
-    es += wgt * (chi * cj + zeta * dj) * mom[j];
-    P.coef[g * P.mstride + j] = cj;
-  }
-  rs = warp_sum(rs);
-  es = warp_sum(es);
-  if (lane == 0) {
-    P.rec[g * SQ_REC + 0] = 2.0 / C.dV * rs;
-    P.rec[g * SQ_REC + 1] = 2.0 * es;
-  }
-}
-
-// Neumaier-compensated fixed-order sum of x[i * stride] over [0, n).
-__device__ void block_neumaier(const double* x, long long n, long long stride, double* out,
-                               double* red_s, double* red_c) {
-  double s = 0.0, c = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
-    const double v = x[i * stride];
-    const double t = s + v;
-    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-    s = t;
-  }
-  red_s[threadIdx.x] = s;
-  red_c[threadIdx.x] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double S = 0.0, Cc = 0.0;
-    for (int i = 0; i < (int)blockDim.x; ++i) {
-      const double v = red_s[i];
-      const double t = S + v;
-      Cc += fabs(S) >= fabs(v) ? (S - t) + v : (v - t) + S;
-      S = t;
-      Cc += red_c[i];
-    }
-    *out = S + Cc;
-  }
-  __syncthreads();
-}
-
-// Fermi-level bracket: [min lam_lo - 40 kT, max lam_hi + 40 kT].
-__global__ void __launch_bounds__(256) k_mu_init(PlanDev P, const int* cells, const int* fixed_mode) {
-  __shared__ double slo[256], shi[256];
-  const int ci = cells[blockIdx.x];
-  const CellDev& C = P.cells[ci];
-  double lo = 1e300, hi = -1e300;
-  for (long long q = threadIdx.x; q < C.Nd; q += blockDim.x) {
-    const double* b = P.bnd + 4 * (C.node_base + q);
-    lo = fmin(lo, b[0]);
-    hi = fmax(hi, b[1]);
-  }
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < 256; ++i) {
-      lo = fmin(lo, slo[i]);
-      hi = fmax(hi, shi[i]);
-    }
-    double* m = P.mus + 8 * ci;
-    m[MU_LO] = lo - 40.0 * C.kT;
-    m[MU_HI] = hi + 40.0 * C.kT;
-    m[MU_IT] = 0.0;
-    m[MU_N] = 0.0;
-    if (fixed_mode[blockIdx.x]) {
-      m[MU_DONE] = 1.0;
-      m[MU_PHASE] = 3.0;
-      m[MU_VAL] = C.mu0;
-      m[MU_MID] = C.mu0;
-    } else {
-      m[MU_DONE] = 0.0;
-      m[MU_PHASE] = 0.0;
-      m[MU_MID] = m[MU_LO];
-    }
-  }
-}
-
-// Electron count of each cell at its trial mu and the bisection update.
-__global__ void __launch_bounds__(256) k_mu_step(PlanDev P, const int* cells) {
-  __shared__ double rs[256], rc[256];
-  __shared__ double tot;
-  const int ci = cells[blockIdx.x];
-  const CellDev& C = P.cells[ci];
-  double* m = P.mus + 8 * ci;
-  if (m[MU_DONE] != 0.0) return;
-  block_neumaier(P.nq + C.node_base, C.Nd, 1, &tot, rs, rc);
-  if (threadIdx.x != 0) return;
-  const double N = 2.0 * tot;
-  const double Ne = C.ne;
-  m[MU_N] = N;
-  const int phase = (int)m[MU_PHASE];
-  if (phase == 0) {
-    if (!(N < Ne)) { m[MU_DONE] = 2.0; return; }
-    m[MU_PHASE] = 1.0;
-    m[MU_MID] = m[MU_HI];
-    return;
-  }
-  if (phase == 1) {
-    if (!(Ne < N)) { m[MU_DONE] = 2.0; return; }
-    m[MU_PHASE] = 2.0;
-    m[MU_MID] = 0.5 * (m[MU_LO] + m[MU_HI]);
-    return;
-  }
-  const double mid = m[MU_MID];
-  if (fabs(N - Ne) <= 1e-13 * Ne) {
-    m[MU_VAL] = mid;
-    m[MU_DONE] = 1.0;
-    return;
-  }
-  if (N < Ne) m[MU_LO] = mid; else m[MU_HI] = mid;
-  m[MU_IT] += 1.0;
-  if (m[MU_IT] >= 200.0) {
-    m[MU_VAL] = 0.5 * (m[MU_LO] + m[MU_HI]);
-    m[MU_DONE] = 1.0;
-    return;
-  }
-  m[MU_MID] = 0.5 * (m[MU_LO] + m[MU_HI]);
-}
-
-__global__ void __launch_bounds__(256) k_reduce(PlanDev P, const int* cells, int col0, int ncol) {
-  __shared__ double rs[256], rc[256];
-  const int ci = cells[blockIdx.x];
-  const CellDev& C = P.cells[ci];
-  for (int c = col0; c < col0 + ncol; ++c) {
-    block_neumaier(P.rec + C.node_base * SQ_REC + c, C.Nd, SQ_REC, P.sums + ci * (SQ_REC + 4) + c,
-                   rs, rc);
-  }
-}
-
-// Local potential on the periodic grid: sum over atom images within v_rcut.
-__global__ void __launch_bounds__(256) k_vloc(const CellDev* cell, double* out) {
-  const CellDev& C = *cell;
-  const long long i = blockIdx.x * 256ll + threadIdx.x;
-  if (i >= C.Nd) return;
-  const long long ix = i % C.n[0], iy = (i / C.n[0]) % C.n[1], iz = i / ((long long)C.n[0] * C.n[1]);
-  double v = 0.0;
-  for (int I = 0; I < C.nimg; ++I) {
-    const double* R = C.img + 4 * I;
-    const SpecDev& s = C.sp[(int)R[3]];
-    const double dx = node_coord(ix, C.h, R[0]);
-    const double dy = node_coord(iy, C.h, R[1]);
-    const double dz = node_coord(iz, C.h, R[2]);
-    const double r2 = sq_add(sq_sum2(dx, dy), dz);
-    if (r2 < s.v_rc * s.v_rc) v += -s.v_amp * exp(-r2 / (2.0 * s.v_sig * s.v_sig));
-  }
-  out[i] = v;
-}
-
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// launchers.  The file is compiled once per cube width (SQ_ONE_NC defined:
-// the templated recurrence kernels of that width) and once without it (the
-// width-independent kernels and the dispatch over widths), so that the
-// widths build in parallel.  Within a width the variant is picked from the
-// slot capacity kc the cell needs (largest number of atom images crossing
-// one z-column of a cube, measured at set-up).
-// ---------------------------------------------------------------------------
-#define SQ_NC_LIST(X) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25)
-
-#define SQ_DECL_NC(N)                                                                          \
-  hipError_t sq_launch_lanczos_##N(int kc, const PlanDev& P, const long long* items,          \
-                                   const int* ic, long long n, hipStream_t s);                \
-  hipError_t sq_launch_moments_##N(bool fp64, int kc, const PlanDev& P, const long long* items, \
-                                   const int* ic, long long n, hipStream_t s);                \
-  hipError_t sq_launch_stress_##N(bool fp64, int kc, const PlanDev& P, const long long* items,  \
-                                  const int* ic, long long n, hipStream_t s);                 \
-  hipError_t sq_launch_census_##N(const PlanDev& P, const long long* items, const int* ic,     \
-                                  long long n, int* stats, long long* pairs, hipStream_t s);
-SQ_NC_LIST(SQ_DECL_NC)
-
-// Largest slot capacity per precision and width (0: unsupported).
-__host__ __device__ constexpr int sq_kc_max(bool, int) { return 48; }
-
-// Largest number of atom images one cube may see (the image index shares a
-// 32-bit slot word with the chord bits of the NC planes).
-__host__ __device__ constexpr int sq_img_max(int nc) { return (1 << (32 - nc)) < 160 ? (1 << (32 - nc)) : 160; }
-
-#ifdef SQ_ONE_NC
 #define SQ_CAT2(a, b) a##b
 #define SQ_CAT(a, b) SQ_CAT2(a, b)
 // Everything below that depends on the width has internal linkage: the
@@ -1452,102 +988,3 @@ hipError_t SQ_CAT(sq_launch_census_, SQ_ONE_NC)(const PlanDev& P, const long lon
                      pairs);
   return hipGetLastError();
 }
-
-#else  // width-independent part
-
-bool sq_nc_supported(int nc) {
-#define SQ_CASE(N) if (nc == N) return true;
-  SQ_NC_LIST(SQ_CASE)
-#undef SQ_CASE
-  return false;
-}
-
-int sq_kc_limit(bool fp64, int nc) { return sq_kc_max(fp64, nc); }
-
-int sq_img_limit(int nc) { return sq_img_max(nc); }
-
-hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
-                             const int* item_cell, long long nitems, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) if (nc == N) return sq_launch_lanczos_##N(kc, P, items, item_cell, nitems, s);
-  SQ_NC_LIST(SQ_CASE)
-#undef SQ_CASE
-  return hipErrorInvalidValue;
-}
-
-hipError_t sq_launch_moments(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
-                             const int* item_cell, long long nitems, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) \
-  if (nc == N) return sq_launch_moments_##N(fp64, kc, P, items, item_cell, nitems, s);
-  SQ_NC_LIST(SQ_CASE)
-#undef SQ_CASE
-  return hipErrorInvalidValue;
-}
-
-hipError_t sq_launch_stress(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
-                            const int* item_cell, long long nitems, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) \
-  if (nc == N) return sq_launch_stress_##N(fp64, kc, P, items, item_cell, nitems, s);
-  SQ_NC_LIST(SQ_CASE)
-#undef SQ_CASE
-  return hipErrorInvalidValue;
-}
-
-hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
-                            long long nitems, int* stats, long long* pairs, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) \
-  if (nc == N) return sq_launch_census_##N(P, items, item_cell, nitems, stats, pairs, s);
-  SQ_NC_LIST(SQ_CASE)
-#undef SQ_CASE
-  return hipErrorInvalidValue;
-}
-
-hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s) {
-  const long long nb = (h_cell.Nd + 255) / 256;
-  hipLaunchKernelGGL(k_vloc, dim3((unsigned)nb), dim3(256), 0, s, d_cell, vloc);
-  return hipGetLastError();
-}
-
-hipError_t sq_launch_bounds(const PlanDev& P, const long long* items, const int* item_cell,
-                            long long nitems, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bounds, dim3((unsigned)((nitems + 127) / 128)), dim3(128), 0, s, P, items,
-                     item_cell, nitems);
-  return hipGetLastError();
-}
-
-hipError_t sq_launch_mu_init(const PlanDev& P, const int* cells, int ncells, const int* fixed_mode,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_mu_init, dim3(ncells), dim3(256), 0, s, P, cells, fixed_mode);
-  return hipGetLastError();
-}
-
-hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int* item_cell,
-                             long long nitems, hipStream_t s) {
-  hipLaunchKernelGGL(k_mu_eval, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, P, items,
-                     item_cell, nitems);
-  return hipGetLastError();
-}
-
-hipError_t sq_launch_mu_step(const PlanDev& P, const int* cells, int ncells, hipStream_t s) {
-  hipLaunchKernelGGL(k_mu_step, dim3(ncells), dim3(256), 0, s, P, cells);
-  return hipGetLastError();
-}
-
-hipError_t sq_launch_coeffs(const PlanDev& P, const long long* items, const int* item_cell,
-                            long long nitems, hipStream_t s) {
-  hipLaunchKernelGGL(k_coeffs, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, P, items,
-                     item_cell, nitems);
-  return hipGetLastError();
-}
-
-hipError_t sq_launch_reduce(const PlanDev& P, const int* cells, int ncells, int col0, int ncol,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(ncells), dim3(256), 0, s, P, cells, col0, ncol);
-  return hipGetLastError();
-}
-
-#endif

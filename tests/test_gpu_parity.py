@@ -175,15 +175,21 @@ def test_batched_uneven_cells_match_single_cell_runs(sq):
         rho_b, mu_b = P.density(-1)
         e_b = P.energy(-1)
         sig_b, parts_b = P.stress(-1)
+    # the same computation in one batched plan or alone: they differ only by
+    # the arrival order of the LDS-atomic projection sums (as repeated runs do)
+    tol = 0.1 * TOL64
     for i, c in enumerate(cells):
         with sq.Plan([c], precision="fp64") as P1:
             rho1, mu1 = P1.density(0)
             e1 = P1.energy(0)
             sig1, _ = P1.stress(0)
-        assert abs(mu_b[i] - mu1[0]) <= 1e-12 * max(1, abs(mu1[0]))
-        assert rel(rho_b[i], rho1[0]) < 1e-12
-        assert abs(e_b[i] - e1[0]) <= 1e-12 * abs(e1[0])
-        assert rel(sig_b[i], sig1[0]) < 1e-11
+        _log("  cell %d batched vs alone: mu %.2e rho %.2e E %.2e sigma %.2e" % (
+            i, abs(mu_b[i] - mu1[0]), rel(rho_b[i], rho1[0]), abs(e_b[i] - e1[0]) / abs(e1[0]),
+            rel(sig_b[i], sig1[0])))
+        assert abs(mu_b[i] - mu1[0]) <= tol * max(1, abs(mu1[0]))
+        assert rel(rho_b[i], rho1[0]) < tol
+        assert abs(e_b[i] - e1[0]) <= tol * abs(e1[0])
+        assert rel(sig_b[i], sig1[0]) < tol
     # one cell of the batch against the oracle on sampled nodes
     c = cells[0]
     n = int(round(c["L"][0] / c["h"])) ** 3
