@@ -62,6 +62,41 @@ def hbm_bytes(info, K):
     return v + mom + coef + lan + rec
 
 
+KERNEL_SOURCES = ("paper_2006_03697_amd/csrc/sq_recur.hip", "paper_2006_03697_amd/csrc/sq_devfn.h",
+                  "paper_2006_03697_amd/csrc/sq_dev.h")
+
+
+def kernel_source_hash():
+    """SHA-1 over the recurrence-kernel sources (identifies the build whose
+    counters a profile summary records)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(phase, precision):
+    """HBM bytes per launch of a kernel from the profile summaries (a line
+    'traffic-json: {...}' with the counters of rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE, scaled by the same counters on a plain copy), if they were
+    taken on the current kernel sources; else None."""
+    import glob
+    want = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(f):
+            if line.startswith("traffic-json:"):
+                try:
+                    rec = json.loads(line.split(":", 1)[1])
+                except ValueError:
+                    continue
+                if rec.get("phase") == phase and rec.get("precision") == precision and \
+                        rec.get("source_sha1") == want:
+                    return float(rec["bytes_per_launch"])
+    return None
+
+
 def run_precision(sq, cell, precision, steps, warmup):
     import torch
     t0 = time.time()
@@ -179,7 +214,8 @@ def main():
                    "precision": head},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": recorded_traffic(dom, head)},
         "hbm": {"achieved": step_bytes / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": step_bytes / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS},
         "phases_ms": {k: v[0] / max(v[1], 1) for k, v in r["phases"].items()},
