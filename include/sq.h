@@ -55,7 +55,18 @@ typedef enum {
   SQ_E_STATE = 6    /* call order violated (e.g. stress before density)     */
 } sq_status;
 
-typedef enum { SQ_FP64 = 0, SQ_MIXED = 1 } sq_precision;
+/* Working precision of the Chebyshev recurrence vectors (Sec. IV).  The
+ * spectral-bound Lanczos, the moments' inner products, the coefficients, the
+ * Fermi level and every reduction are FP64 in all modes.
+ *   SQ_FP64          FP64 vectors in both passes.
+ *   SQ_MIXED         FP32 vectors in the moments pass and in the stress pass.
+ *   SQ_MIXED_STRESS  FP64 vectors in the moments pass (so mu, rho and the
+ *                    band energy are those of SQ_FP64), FP32 vectors in the
+ *                    stress pass.  For cells whose Fermi level is
+ *                    ill-conditioned (low density of states at mu) the FP32
+ *                    moments of SQ_MIXED shift mu and through it the stress;
+ *                    this mode avoids that at the cost of the FP64 moments. */
+typedef enum { SQ_FP64 = 0, SQ_MIXED = 1, SQ_MIXED_STRESS = 2 } sq_precision;
 typedef enum { SQ_MU_SOLVE = 0, SQ_MU_FIXED = 1 } sq_mu_mode;
 
 /* One analytic species (the paper's pseudopotential data, Sec. V.A, is

@@ -431,7 +431,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   if (!out) return fail(nullptr, SQ_E_ARG, "out is NULL");
   *out = nullptr;
   if (!cells || n_cells < 1 || !opt) return fail(nullptr, SQ_E_ARG, "cells / options missing");
-  if (opt->precision != SQ_FP64 && opt->precision != SQ_MIXED)
+  if (opt->precision != SQ_FP64 && opt->precision != SQ_MIXED && opt->precision != SQ_MIXED_STRESS)
     return fail(nullptr, SQ_E_ARG, "unknown precision");
   sq_plan p = new sq_plan_s();
   p->opt = *opt;
@@ -548,7 +548,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
       st = check_hip(p, hipMemcpyAsync(pairs.data(), d_pairs, sizeof(long long) * pairs.size(),
                                        hipMemcpyDeviceToHost, p->stream), "census copy");
     if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(p->stream), "census");
-    const bool fp64 = p->opt.precision == SQ_FP64;
+    const bool fp64 = p->opt.precision == SQ_FP64;   // both passes FP64
     for (int i = 0; i < n_cells && st == SQ_OK; ++i) {
       CellHost& c = p->cells[i];
       c.census_img = stats[4 * i];
@@ -661,7 +661,7 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
   if (st != SQ_OK) return st;
-  const bool fp64 = p->opt.precision == SQ_FP64;
+  const bool fp64 = p->opt.precision != SQ_MIXED;   // precision of the moments pass
   hipStream_t s = p->stream;
   st = check_hip(p, hipMemsetAsync(p->P.err, 0, sizeof(unsigned), s), "memset");
   phase_begin(p, PH_LANCZOS);

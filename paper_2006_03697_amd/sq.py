@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SQ_LIB_PATH") or os.path.join(HERE, "libsq_mi355x.so")
 
 SQ_OK, SQ_E_ARG, SQ_E_ALLOC, SQ_E_DEVICE, SQ_E_BOUNDS, SQ_E_NOCONV, SQ_E_STATE = range(7)
-SQ_FP64, SQ_MIXED = 0, 1
+SQ_FP64, SQ_MIXED, SQ_MIXED_STRESS = 0, 1, 2
+PRECISIONS = {"fp64": SQ_FP64, "mixed": SQ_MIXED, "mixed_stress": SQ_MIXED_STRESS}
 SQ_MU_SOLVE, SQ_MU_FIXED = 0, 1
 REC = 20
 
@@ -183,7 +184,9 @@ class Plan:
         for i, c in enumerate(self.cells):
             arr[i] = _cell_struct(c, self._keep)
         opt = SqOptions()
-        opt.precision = SQ_MIXED if precision == "mixed" else SQ_FP64
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % ", ".join(PRECISIONS))
+        opt.precision = PRECISIONS[precision]
         opt.hip_stream = ctypes.c_void_p(stream.cuda_stream)
         self._alloc = _TorchAllocator(self.device) if use_torch_memory else None
         if self._alloc is not None:

@@ -98,6 +98,13 @@ def test_tiny_cell_mixed(sq):
     assert err["rho"] < 1e-3 and err["e_band"] < 1e-4
 
 
+def test_tiny_cell_mixed_stress(sq):
+    err, ref, g = _full_compare(sq, W.tiny_cell(), "mixed_stress", "tiny 12^3 nodes, 9^3 cube")
+    # FP64 moments: Fermi level, density and band energy as in FP64
+    assert err["mu"] < TOL64 and err["rho"] < TOL64 and err["e_band"] < TOL64
+    assert err["sigma_abs"] < TOL_MIXED_SIGMA
+
+
 def test_ragged_cell_fp64_every_node(sq):
     # 17^3 nodes (ragged node tiles), 15^3 cubes, several atoms
     cell = W.random_cell(seed=11, L=6.8, h=0.4, n_atoms=6, d_min=1.5, rcut=3.0, npl=30, kT=0.1)
@@ -229,3 +236,112 @@ def test_repeat_runs_agree(sq):
     assert abs(m1[0] - m2[0]) <= 0.1 * TOL64 * max(1.0, abs(m1[0]))
     assert rel(r1[0], r2[0]) < 0.1 * TOL64
     assert rel(s1[0], s2[0]) < 0.1 * TOL64
+
+
+@pytest.mark.parametrize("npl", [40, 60, 80])
+def test_mixed_precision_degree_sweep(sq, npl):
+    # 64000-node cell with the Chebyshev degree swept: the mixed path (FP32
+    # recurrence, FP64 accumulation) against the FP64 path, which is itself
+    # checked against the oracle on sampled nodes
+    cell = W.fp64_cell(npl=npl)
+    _log("case degree sweep npl=%d (40^3 nodes, 21^3 cube)" % npl)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        with sq.Plan([cell], precision=prec) as P:
+            rho, mu = P.density(0)
+            e = P.energy(0)
+            sig, parts = P.stress(0)
+            rec = P.nodes(0, W.node_sample(64000, 4, seed=43)) if prec == "fp64" else None
+        out[prec] = dict(rho=rho[0], mu=mu[0], e=e[0], sig=sig[0], rec=rec)
+    f, m = out["fp64"], out["mixed"]
+    ref = O.run(cell, nodes=W.node_sample(64000, 4, seed=43), mu=float(f["mu"]))
+    err64 = _records_rel(f["rec"], ref["records"])
+    errs = dict(mu=abs(m["mu"] - f["mu"]), rho_max=rel(m["rho"], f["rho"]),
+                rho_rms=float(np.sqrt(np.mean((m["rho"] - f["rho"]) ** 2)) / np.max(np.abs(f["rho"]))),
+                e_band=abs(m["e"] - f["e"]) / abs(f["e"]),
+                sigma_abs=[float(x) for x in np.abs(m["sig"] - f["sig"])])
+    _log("  fp64 vs oracle (4 nodes)", {k: "%.2e" % v for k, v in err64.items()})
+    _log("  mixed vs fp64: mu %.2e rho max %.2e rms %.2e E %.2e sigma %s" % (
+        errs["mu"], errs["rho_max"], errs["rho_rms"], errs["e_band"],
+        " ".join("%.2e" % x for x in errs["sigma_abs"])))
+    for k, v in err64.items():
+        assert v < TOL64, (k, v)
+    assert max(errs["sigma_abs"]) < TOL_MIXED_SIGMA
+    assert errs["rho_max"] < 1e-2 and errs["e_band"] < 1e-3
+
+
+def test_batched_32_uneven_cells_mixed_and_fp64(sq):
+    # the 32-cell stream (8-64 atoms, 10-16 Bohr, R_cut 3-4, degree 30-80,
+    # kT 0.03-0.2) in one plan per precision; the densest cell needs the
+    # 48-slot variant
+    cells = W.batched_cells(n_cells=32, seed=3)
+    _log("case batched 32 cells, %d nodes" % sum(round(c["L"][0] / c["h"]) ** 3 for c in cells))
+    res = {}
+    for prec in ("fp64", "mixed", "mixed_stress"):
+        import time
+        t0 = time.time()
+        with sq.Plan(cells, precision=prec) as P:
+            rho, mu = P.density(-1)
+            e = P.energy(-1)
+            sig, parts = P.stress(-1)
+            recs = {ci: P.nodes(ci, W.node_sample(round(cells[ci]["L"][0] / cells[ci]["h"]) ** 3, 3, seed=44))
+                    for ci in (0, 5)} if prec == "fp64" else None
+        res[prec] = dict(rho=rho, mu=mu, e=e, sig=sig, recs=recs)
+        _log("  %s: %.1f s" % (prec, time.time() - t0))
+    worst = {"mixed": 0.0, "mixed_stress": 0.0}
+    for i in range(len(cells)):
+        d = {k: float(np.max(np.abs(res[k]["sig"][i] - res["fp64"]["sig"][i]))) for k in worst}
+        for k in worst:
+            worst[k] = max(worst[k], d[k])
+        _log("  cell %2d: |sigma| %.3e  mixed-fp64 %.2e (mu %.2e)  mixed_stress-fp64 %.2e (mu %.2e)"
+             "  npl %d kT %.3f atoms %d n %d" % (
+                 i, float(np.max(np.abs(res["fp64"]["sig"][i]))), d["mixed"],
+                 abs(res["mixed"]["mu"][i] - res["fp64"]["mu"][i]), d["mixed_stress"],
+                 abs(res["mixed_stress"]["mu"][i] - res["fp64"]["mu"][i]), cells[i]["npl"],
+                 cells[i]["kT"], len(cells[i]["pos"]), round(cells[i]["L"][0] / cells[i]["h"])))
+    _log("  worst sigma abs: mixed %.2e  mixed_stress %.2e" % (worst["mixed"], worst["mixed_stress"]))
+    # FP64 moments: mu as in FP64, the FP32 stress pass within the target
+    assert worst["mixed_stress"] < TOL_MIXED_SIGMA
+    # FP32 moments: in a cell with few states at the Fermi level (15 atoms,
+    # kT 0.047) the moments' FP32 error moves mu by ~5e-6 Ha and sigma by
+    # ~2.5e-6; the bound guards against regressions beyond that
+    assert worst["mixed"] < 5 * TOL_MIXED_SIGMA
+    for ci in (0, 5):
+        c = cells[ci]
+        nodes = W.node_sample(round(c["L"][0] / c["h"]) ** 3, 3, seed=44)
+        ref = O.run(c, nodes=nodes, mu=float(res["fp64"]["mu"][ci]))
+        err = _records_rel(res["fp64"]["recs"][ci], ref["records"])
+        _log("  cell %d fp64 vs oracle" % ci, {k: "%.2e" % v for k, v in err.items()})
+        for k, v in err.items():
+            assert v < TOL64, (ci, k, v)
+
+
+def test_512000_node_cell_mixed_vs_fp64(sq):
+    # 80^3 nodes, 25^3 cubes, degree 80, 512 atoms: the mixed path against
+    # the FP64 path; the FP64 path against the oracle on sampled nodes at
+    # its Fermi level
+    import time
+    cell = W.large_cell()
+    _log("case 512000-node cell (80^3 nodes, 25^3 cube, npl 80)")
+    out = {}
+    nodes = W.node_sample(512000, 4, seed=45)
+    for prec in ("fp64", "mixed"):
+        t0 = time.time()
+        with sq.Plan([cell], precision=prec) as P:
+            rho, mu = P.density(0)
+            e = P.energy(0)
+            sig, parts = P.stress(0)
+            rec = P.nodes(0, nodes)
+        out[prec] = dict(rho=rho[0], mu=mu[0], e=e[0], sig=sig[0], rec=rec)
+        _log("  %s: %.1f s  mu %.12f  sigma %s" % (prec, time.time() - t0, mu[0],
+                                                   np.array2string(sig[0], precision=8)))
+    ref = O.run(cell, nodes=nodes, mu=float(out["fp64"]["mu"]))
+    err = _records_rel(out["fp64"]["rec"], ref["records"])
+    _log("  fp64 vs oracle (4 nodes)", {k: "%.2e" % v for k, v in err.items()})
+    for k, v in err.items():
+        assert v < TOL64, (k, v)
+    ds = float(np.max(np.abs(out["mixed"]["sig"] - out["fp64"]["sig"])))
+    _log("  mixed vs fp64: sigma abs %.2e  rho %.2e  E %.2e" % (
+        ds, rel(out["mixed"]["rho"], out["fp64"]["rho"]),
+        abs(out["mixed"]["e"] - out["fp64"]["e"]) / abs(out["fp64"]["e"])))
+    assert ds < TOL_MIXED_SIGMA
