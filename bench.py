@@ -4,7 +4,8 @@
 A step is one pass of the whole hot path over one cell already resident in
 HBM: spectral bounds (FP64 Lanczos), Chebyshev moments, Fermi level,
 Clenshaw-Curtis coefficients and density (sq_density), band energy
-(sq_energy) and the kinetic + nonlocal stress pass (sq_stress).  The plan
+(sq_energy), the kinetic + nonlocal stress pass (sq_stress) and the direct
+and trace pressures from its sums (sq_pressure).  The plan
 (grid, atom images, local potential, capacity census) is built before the
 timed region.  Default workload: the 64000-node cell (16 Bohr cube, h = 0.4,
 64 atoms, 21^3 cubes, degree 60, kT = 0.05 Ha).
@@ -58,7 +59,7 @@ def hbm_bytes(info, K):
     mom = 8 * Nd * (npl + 1) * 2       # moments written, read by coefficients
     coef = 8 * Nd * (npl + 1) * 2      # coefficients written, read by the stress pass
     lan = 8 * Nd * 2 * K               # Lanczos tridiagonals
-    rec = 8 * Nd * 20                  # per-node records
+    rec = 8 * Nd * 22                  # per-node records
     return v + mom + coef + lan + rec
 
 
@@ -108,6 +109,7 @@ def run_precision(sq, cell, precision, steps, warmup):
         plan.density_only(0)
         plan.energy(0)
         plan.stress(0)
+        plan.pressure(0)
 
     for _ in range(warmup):
         step()
@@ -121,10 +123,11 @@ def run_precision(sq, cell, precision, steps, warmup):
     ph = plan.phase_times(reset=True)
     _, mu = plan.density(0)
     sig, _ = plan.stress(0)
+    pd, pt = plan.pressure(0)
     plan.close()
     ms = (t1 - t0) * 1000.0 / steps
     return dict(ms=ms, setup_s=setup_s, info=info, phases=ph, mu=float(mu[0]),
-                sigma=[float(x) for x in sig[0]])
+                sigma=[float(x) for x in sig[0]], p_direct=float(pd[0]), p_trace=float(pt[0]))
 
 
 def cpu_baseline(cell, mu, sample):
@@ -221,6 +224,7 @@ def main():
                 "unit": "GB/s", "frac": step_bytes / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS},
         "phases_ms": {k: v[0] / max(v[1], 1) for k, v in r["phases"].items()},
         "setup_s": r["setup_s"],
+        "pressure": {"direct": r["p_direct"], "trace": r["p_trace"], "unit": "Ha/Bohr^3"},
     }
     for mk in ("mixed", "mixed_stress"):
         if mk not in res or head != "fp64":
@@ -234,7 +238,8 @@ def main():
                    "phases_ms": {k: v[0] / max(v[1], 1) for k, v in m["phases"].items()},
                    "stress_tflops": mf["stress"] / (mpl["stress"] * 1e-3) / 1e12,
                    "mu_diff_vs_fp64": abs(m["mu"] - r["mu"]),
-                   "sigma_diff_vs_fp64": max(abs(a - b) for a, b in zip(m["sigma"], r["sigma"]))}
+                   "sigma_diff_vs_fp64": max(abs(a - b) for a, b in zip(m["sigma"], r["sigma"])),
+                   "p_direct_diff_vs_fp64": abs(m["p_direct"] - r["p_direct"])}
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(cell, r["mu"], args.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -13,8 +13,8 @@
  * Fermi-Dirac coefficients c_q^j, gives the density-matrix column
  * d_q = sum' c_q^j t^j, from which the electron density
  * rho_q = (2/dV) sum' c_q^j rho_q^j, the band energy
- * 2 sum_q sum' (chi_q c_q^j + zeta_q d_q^j) rho_q^j and the kinetic and
- * nonlocal density-matrix stress follow.
+ * 2 sum_q sum' (chi_q c_q^j + zeta_q d_q^j) rho_q^j, the kinetic and
+ * nonlocal density-matrix stress and the pressure follow.
  *
  * Units: Hartree atomic units (Ha, Bohr).  All host-side scalars and arrays
  * are IEEE binary64 unless stated otherwise.
@@ -131,9 +131,28 @@ sq_status sq_energy(sq_plan plan, int cell, double* e_band);
  * of K (3x3) then N (3x3), not divided by |Omega|.  Needs sq_density. */
 sq_status sq_stress(sq_plan plan, int cell, double* sigma_voigt, double* parts);
 
-/* Per-node records for a list of nodes of one cell: out [n][20] =
- * rho_q, band-energy density e_q, K (9), N (9).  K and N need sq_stress
- * first (zeros otherwise).  nodes are host arrays. */
+/* Pressure, P = -(sigma_11 + sigma_22 + sigma_33)/3 of the kinetic + nonlocal
+ * stress, one value per cell in each output (either may be NULL), in two
+ * forms:
+ *   p_direct  the direct form of App. A: the kinetic trace is taken from the
+ *             band energy, -2 E_band + 2 sum_q dV V_q rho_q + 2 E_nl (the
+ *             Chebyshev expansion of H times the density matrix), so no
+ *             second derivative of the density matrix enters; the nonlocal
+ *             part is tr N.  P = -(that + tr N) / (3 |Omega|), with
+ *             E_nl = 2 sum_q sum_I gamma dV chi_I(x_q) chi_I^T d_q.
+ *   p_trace   -tr(K + N) / (3 |Omega|) from the stress of sq_stress.
+ * The two agree to the discretisation and truncation error (the 12th-order
+ * Laplacian is not the square of the 12th-order gradient, and the expansion
+ * of x g(x) stops at degree n_pl).  Runs the stress pass first when
+ * sq_stress has not run since the last sq_density; needs sq_density
+ * (SQ_E_STATE otherwise). */
+sq_status sq_pressure(sq_plan plan, int cell, double* p_direct, double* p_trace);
+
+/* Per-node records for a list of nodes of one cell: out [n][22] =
+ * rho_q, band-energy density e_q, K (9), N (9), nonlocal energy density
+ * 2 sum_I gamma dV chi_I(x_q) chi_I^T d_q, local-potential energy
+ * dV V_q rho_q.  K, N and the nonlocal energy need the stress pass after the
+ * last sq_density (zeros otherwise).  nodes are host arrays. */
 sq_status sq_nodes(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
 /* Per-node spectral bounds lambda_lo, lambda_hi ([N_d] each, host arrays),

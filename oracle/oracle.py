@@ -18,6 +18,8 @@ Paper: Sharma, Hamel, Bethkenhagen, Pask, Suryanarayana, arXiv 2006.03697.
   * rho_q = (2/dV) sum' c_q^j rho_q^j, rho_q^j = w_q^T t_q^j   -- Sec. IV
   * band-energy trace sum'(chi_q c_q^j + zeta_q d_q^j) rho_q^j -- App. A
   * SQ kinetic + nonlocal stress                             -- Sec. IV
+  * direct pressure from the band energy, no second
+    derivatives of the density matrix                        -- App. A
 
 Readings of what the paper leaves open (also listed in the design notes):
   R1 spectral bounds: K-step FP64 Lanczos from w_q, no reorthogonalisation,
@@ -393,7 +395,13 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
 
     nodes=None: every node; mu from the electron count unless the cell's
     mu_mode is "fixed" or ``mu`` is given.  With a node subset the Fermi level
-    must be given (a subset cannot fix it)."""
+    must be given (a subset cannot fix it).
+
+    records[i] = rho_q, band-energy density e_q, K (9), N (9), nonlocal
+    energy density, local-potential energy density dV V_q rho_q.  With the
+    stress: sigma = (sum K + sum N) / |Omega| and the pressures
+      P_direct = -(-2 E_band + 2 sum_q dV V_q rho_q + 2 E_nl + tr N) / (3 |Omega|)
+      P_trace  = -tr(K + N) / (3 |Omega|)."""
     oc = OracleCell(cell)
     all_nodes = nodes is None
     nodes = oc.nodes_all() if all_nodes else np.ascontiguousarray(nodes, dtype=np.int64)
@@ -409,10 +417,11 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
             raise ValueError("a node subset needs a given Fermi level")
     c, d = node_coefficients(oc, mu, chi, zeta)
     n = len(nodes)
-    rec = np.zeros((n, 20))
+    rec = np.zeros((n, 22))
     for i in range(n):
         rec[i, 0] = 2.0 / oc.dV * primed(c[i], mom[i])
         rec[i, 1] = 2.0 * primed(chi[i] * c[i] + zeta[i] * d[i], mom[i])
+        rec[i, 21] = oc.dV * oc.vloc[nodes[i]] * rec[i, 0]
     res = Result(mu=mu, mu_iterations=it, nodes=nodes, lam_lo=lo, lam_hi=hi, chi=chi, zeta=zeta,
                  moments=mom, coef=c, dcoef=d, rho=rec[:, 0].copy(), e_node=rec[:, 1].copy(),
                  volume=oc.volume, dV=oc.dV)
@@ -431,5 +440,16 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
                                        0.5 * (sig[0, 2] + sig[2, 0]),
                                        0.5 * (sig[0, 1] + sig[1, 0])])
         res["e_nl"] = math.fsum(st[:, 18])
+        rec[:, 20] = st[:, 18]
+        # direct pressure (App. A) restricted to the kinetic + nonlocal terms:
+        # the kinetic trace comes from the band energy with the local and
+        # nonlocal potential energies taken back out, the nonlocal part is
+        # tr N; the trace form is -tr(K + N) / 3 of the stress
+        res["v_rho"] = math.fsum(rec[:, 21])
+        trK = parts[0] + parts[4] + parts[8]
+        trN = parts[9] + parts[13] + parts[17]
+        res["pressure_direct"] = -(-2.0 * res["e_band"] + 2.0 * res["v_rho"] + 2.0 * res["e_nl"]
+                                   + trN) / (3.0 * oc.volume)
+        res["pressure_trace"] = -(trK + trN) / (3.0 * oc.volume)
     res["records"] = rec
     return res

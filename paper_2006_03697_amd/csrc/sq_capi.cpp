@@ -393,6 +393,48 @@ sq_status copy_out(sq_plan p, void* dst, const void* src, size_t bytes) {
   return check_hip(p, hipMemcpyAsync(dst, src, bytes, k, p->stream), "copy");
 }
 
+// Host value(s) to a caller's output buffer (device or host per the options).
+sq_status put_out(sq_plan p, void* dst, const void* src, size_t bytes) {
+  if (p->opt.outputs_on_device) return check_hip(p, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "output");
+  std::memcpy(dst, src, bytes);
+  return SQ_OK;
+}
+
+// Reduced per-cell records (every cell of the plan) to the host.
+sq_status read_sums(sq_plan p, std::vector<double>& sums) {
+  sums.assign((SQ_REC + 4) * p->cells.size(), 0.0);
+  sq_status st = check_hip(p, hipMemcpyAsync(sums.data(), p->P.sums, sizeof(double) * sums.size(),
+                                             hipMemcpyDeviceToHost, p->stream), "sums");
+  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(p->stream), "sums");
+  return st;
+}
+
+// The stress pass over a selection: density-matrix columns, their gradients,
+// K and N per node, the nonlocal energy per node, and the node sums of those
+// columns.  Marks the cells' stress as done.
+sq_status stress_pass(sq_plan p, Selection* S, std::vector<double>& sums) {
+  for (int ci : S->cells)
+    if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_stress / sq_pressure before sq_density");
+  const bool fp64 = p->opt.precision == SQ_FP64;
+  hipStream_t s = p->stream;
+  sq_status st = check_hip(p, hipMemsetAsync(p->P.err, 0, sizeof(unsigned), s), "memset");
+  phase_begin(p, PH_STRESS);
+  for (const Group& g : S->groups)
+    if (st == SQ_OK)
+      st = check_hip(p, sq_launch_stress(g.nc, g.kc, fp64, p->P, g.items, g.cell, g.n, s), "stress");
+  phase_end(p, PH_STRESS);
+  phase_begin(p, PH_REDUCE);
+  if (st == SQ_OK)
+    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 2, 19, s), "reduce");
+  phase_end(p, PH_REDUCE);
+  if (st == SQ_OK) st = check_errors(p);
+  phase_collect(p);
+  if (st == SQ_OK) st = read_sums(p, sums);
+  if (st == SQ_OK)
+    for (int ci : S->cells) p->stress_done[ci] = 1;
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -754,20 +796,12 @@ sq_status sq_energy(sq_plan p, int cell, double* e_band) {
   phase_begin(p, PH_REDUCE);
   st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 1, 1, s), "reduce");
   phase_end(p, PH_REDUCE);
-  std::vector<double> sums((SQ_REC + 4) * p->cells.size());
-  if (st == SQ_OK)
-    st = check_hip(p, hipMemcpyAsync(sums.data(), p->P.sums, sizeof(double) * sums.size(),
-                                     hipMemcpyDeviceToHost, s), "sums");
-  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "energy");
+  std::vector<double> sums;
+  if (st == SQ_OK) st = read_sums(p, sums);
   phase_collect(p);
   if (st != SQ_OK || !e_band) return st;
-  for (size_t i = 0; i < S->cells.size(); ++i) {
-    const double v = sums[(SQ_REC + 4) * S->cells[i] + 1];
-    if (p->opt.outputs_on_device)
-      st = check_hip(p, hipMemcpy(e_band + i, &v, sizeof(double), hipMemcpyHostToDevice), "e");
-    else
-      e_band[i] = v;
-  }
+  for (size_t i = 0; i < S->cells.size() && st == SQ_OK; ++i)
+    st = put_out(p, e_band + i, &sums[(SQ_REC + 4) * S->cells[i] + 1], sizeof(double));
   return st;
 }
 
@@ -776,27 +810,8 @@ sq_status sq_stress(sq_plan p, int cell, double* sigma_voigt, double* parts) {
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
   if (st != SQ_OK) return st;
-  for (int ci : S->cells)
-    if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_stress before sq_density");
-  const bool fp64 = p->opt.precision == SQ_FP64;
-  hipStream_t s = p->stream;
-  st = check_hip(p, hipMemsetAsync(p->P.err, 0, sizeof(unsigned), s), "memset");
-  phase_begin(p, PH_STRESS);
-  for (const Group& g : S->groups)
-    if (st == SQ_OK)
-      st = check_hip(p, sq_launch_stress(g.nc, g.kc, fp64, p->P, g.items, g.cell, g.n, s), "stress");
-  phase_end(p, PH_STRESS);
-  phase_begin(p, PH_REDUCE);
-  if (st == SQ_OK)
-    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 2, 18, s), "reduce");
-  phase_end(p, PH_REDUCE);
-  if (st == SQ_OK) st = check_errors(p);
-  phase_collect(p);
-  std::vector<double> sums((SQ_REC + 4) * p->cells.size());
-  if (st == SQ_OK)
-    st = check_hip(p, hipMemcpyAsync(sums.data(), p->P.sums, sizeof(double) * sums.size(),
-                                     hipMemcpyDeviceToHost, s), "sums");
-  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "stress");
+  std::vector<double> sums;
+  st = stress_pass(p, S, sums);
   if (st != SQ_OK) return st;
   for (size_t i = 0; i < S->cells.size(); ++i) {
     const int ci = S->cells[i];
@@ -806,15 +821,47 @@ sq_status sq_stress(sq_plan p, int cell, double* sigma_voigt, double* parts) {
     for (int t = 0; t < 9; ++t) sg[t] = (pr[t] + pr[9 + t]) / vol;
     double v6[6] = {sg[0], sg[4], sg[8], 0.5 * (sg[5] + sg[7]), 0.5 * (sg[2] + sg[6]),
                     0.5 * (sg[1] + sg[3])};
-    if (p->opt.outputs_on_device) {
-      if (sigma_voigt) st = check_hip(p, hipMemcpy(sigma_voigt + 6 * i, v6, sizeof(v6), hipMemcpyHostToDevice), "sig");
-      if (parts && st == SQ_OK)
-        st = check_hip(p, hipMemcpy(parts + 18 * i, pr, sizeof(double) * 18, hipMemcpyHostToDevice), "parts");
-    } else {
-      if (sigma_voigt) std::memcpy(sigma_voigt + 6 * i, v6, sizeof(v6));
-      if (parts) std::memcpy(parts + 18 * i, pr, sizeof(double) * 18);
-    }
-    p->stress_done[ci] = 1;
+    if (sigma_voigt && st == SQ_OK) st = put_out(p, sigma_voigt + 6 * i, v6, sizeof(v6));
+    if (parts && st == SQ_OK) st = put_out(p, parts + 18 * i, pr, sizeof(double) * 18);
+  }
+  return st;
+}
+
+sq_status sq_pressure(sq_plan p, int cell, double* p_direct, double* p_trace) {
+  if (!p) return SQ_E_ARG;
+  Selection* S = nullptr;
+  sq_status st = select(p, cell, &S);
+  if (st != SQ_OK) return st;
+  bool need = false;
+  for (int ci : S->cells) need = need || !p->stress_done[ci];
+  std::vector<double> sums;
+  if (need) {
+    st = stress_pass(p, S, sums);
+  } else {
+    for (int ci : S->cells)
+      if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_pressure before sq_density");
+  }
+  // band energy and local-potential energy columns (the stress columns are
+  // reduced by the stress pass)
+  hipStream_t s = p->stream;
+  phase_begin(p, PH_REDUCE);
+  if (st == SQ_OK)
+    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 1, 1, s), "reduce");
+  if (st == SQ_OK)
+    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 21, 1, s), "reduce");
+  phase_end(p, PH_REDUCE);
+  if (st == SQ_OK) st = read_sums(p, sums);
+  phase_collect(p);
+  if (st != SQ_OK) return st;
+  for (size_t i = 0; i < S->cells.size(); ++i) {
+    const int ci = S->cells[i];
+    const double* r = &sums[(SQ_REC + 4) * ci];
+    const double vol3 = 3.0 * p->cells[ci].vol;
+    const double trK = r[2] + r[6] + r[10], trN = r[11] + r[15] + r[19];
+    const double pd = -(-2.0 * r[1] + 2.0 * r[21] + 2.0 * r[20] + trN) / vol3;
+    const double pt = -(trK + trN) / vol3;
+    if (p_direct && st == SQ_OK) st = put_out(p, p_direct + i, &pd, sizeof(double));
+    if (p_trace && st == SQ_OK) st = put_out(p, p_trace + i, &pt, sizeof(double));
   }
   return st;
 }

@@ -239,10 +239,15 @@ __global__ void __launch_bounds__(256) k_coeffs(PlanDev P, const long long* item
   }
   rs = warp_sum(rs);
   es = warp_sum(es);
+  // rho, band-energy density, local-potential energy dV V_q rho_q; the
+  // stress columns (K, N, nonlocal energy) start at zero until the stress pass
+  double* rec = P.rec + g * SQ_REC;
   if (lane == 0) {
-    P.rec[g * SQ_REC + 0] = 2.0 / C.dV * rs;
-    P.rec[g * SQ_REC + 1] = 2.0 * es;
+    rec[0] = 2.0 / C.dV * rs;
+    rec[1] = 2.0 * es;
+    rec[21] = 2.0 * C.vloc[g - C.node_base] * rs;
   }
+  if (lane >= 2 && lane <= 20) rec[lane] = 0.0;
 }
 
 // Neumaier-compensated fixed-order sum of x[i * stride] over [0, n).

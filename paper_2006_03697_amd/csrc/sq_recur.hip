@@ -837,16 +837,18 @@ __global__ void __launch_bounds__(Vr::L::NT) k_stress(PlanDev P, const long long
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double N[9];
+    double N[9], enl = 0.0;
     for (int t = 0; t < 9; ++t) N[t] = 0.0;
     for (int n = 0; n < nnear; ++n) {
       const int i = S.near_img[n];
       const double f = -2.0 * S.gdv[i] * S.near_chi[n];
+      enl -= f * S.nsum[n][0];   // 2 gamma dV chi_I(x_q) chi_I^T d_q
       for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
           N[3 * a + b] += f * ((a == b ? S.nsum[n][0] : 0.0) + 2.0 * S.nsum[n][1 + 3 * a + b]);
     }
     for (int t = 0; t < 9; ++t) rec[11 + t] = N[t];
+    rec[20] = enl;
   }
 }
 

@@ -47,12 +47,16 @@ def rel(a, b):
 
 
 def _records_rel(gpu, ora):
-    """Per-field relative errors of [rho, e, K(9), N(9)] record blocks."""
+    """Per-field relative errors of [rho, e, K(9), N(9), e_nl, dV V rho]
+    record blocks."""
     out = {}
     out["rho_q"] = rel(gpu[:, 0], ora[:, 0])
     out["e_q"] = rel(gpu[:, 1], ora[:, 1])
     out["K"] = rel(gpu[:, 2:11], ora[:, 2:11])
     out["N"] = rel(gpu[:, 11:20], ora[:, 11:20])
+    if ora.shape[1] > 20:
+        out["e_nl_q"] = rel(gpu[:, 20], ora[:, 20])
+        out["vrho_q"] = rel(gpu[:, 21], ora[:, 21])
     return out
 
 
@@ -63,6 +67,7 @@ def _full_compare(sq, cell, precision, name):
         rho, mu = P.density(0)
         e = P.energy(0)
         sig, parts = P.stress(0)
+        pd, pt = P.pressure(0)
         rec = P.nodes(0, range(P.n_nodes(0)))
         lo, hi = P.bounds(0)
         mom = P.moments(0, range(P.n_nodes(0)))
@@ -72,13 +77,19 @@ def _full_compare(sq, cell, precision, name):
                rho=rel(rho[0], ref["rho"]), e_band=abs(e[0] - ref["e_band"]) / abs(ref["e_band"]),
                sigma=rel(sig[0], ref["sigma_voigt"]),
                sigma_abs=float(np.max(np.abs(sig[0] - ref["sigma_voigt"]))),
-               K=rel(parts[0][:9], ref["parts"][:9]), N=rel(parts[0][9:], ref["parts"][9:]))
+               K=rel(parts[0][:9], ref["parts"][:9]), N=rel(parts[0][9:], ref["parts"][9:]),
+               p_direct=abs(pd[0] - ref["pressure_direct"]) / abs(ref["pressure_direct"]),
+               p_trace=abs(pt[0] - ref["pressure_trace"]) / abs(ref["pressure_trace"]),
+               p_abs=max(abs(pd[0] - ref["pressure_direct"]), abs(pt[0] - ref["pressure_trace"])))
     err.update({"rec_" + k: v for k, v in _records_rel(rec, ref["records"]).items()})
     _log("  errors", {k: "%.2e" % v for k, v in err.items()})
     _log("  mu gpu %.15g oracle %.15g; sigma gpu %s oracle %s" % (
         mu[0], ref["mu"], np.array2string(sig[0], precision=10),
         np.array2string(ref["sigma_voigt"], precision=10)))
-    return err, ref, dict(rho=rho[0], mu=mu[0], e=e[0], sig=sig[0], parts=parts[0], rec=rec)
+    _log("  pressure gpu direct %.15g trace %.15g; oracle direct %.15g trace %.15g" % (
+        pd[0], pt[0], ref["pressure_direct"], ref["pressure_trace"]))
+    return err, ref, dict(rho=rho[0], mu=mu[0], e=e[0], sig=sig[0], parts=parts[0], rec=rec,
+                          p_direct=pd[0], p_trace=pt[0])
 
 
 def test_tiny_cell_fp64_every_node(sq):
@@ -88,13 +99,15 @@ def test_tiny_cell_fp64_every_node(sq):
     assert err["lam_lo"] < TOL64 and err["lam_hi"] < TOL64
     assert err["moments"] < TOL64
     assert err["mu"] < TOL64
-    for k in ("rho", "e_band", "sigma", "K", "N", "rec_rho_q", "rec_e_q", "rec_K", "rec_N"):
+    for k in ("rho", "e_band", "sigma", "K", "N", "rec_rho_q", "rec_e_q", "rec_K", "rec_N",
+              "rec_e_nl_q", "rec_vrho_q", "p_direct", "p_trace"):
         assert err[k] < TOL64, (k, err[k])
 
 
 def test_tiny_cell_mixed(sq):
     err, ref, g = _full_compare(sq, W.tiny_cell(), "mixed", "tiny 12^3 nodes, 9^3 cube")
     assert err["sigma_abs"] < TOL_MIXED_SIGMA
+    assert err["p_abs"] < TOL_MIXED_SIGMA
     assert err["rho"] < 1e-3 and err["e_band"] < 1e-4
 
 
@@ -103,13 +116,15 @@ def test_tiny_cell_mixed_stress(sq):
     # FP64 moments: Fermi level, density and band energy as in FP64
     assert err["mu"] < TOL64 and err["rho"] < TOL64 and err["e_band"] < TOL64
     assert err["sigma_abs"] < TOL_MIXED_SIGMA
+    assert err["p_abs"] < TOL_MIXED_SIGMA
 
 
 def test_ragged_cell_fp64_every_node(sq):
     # 17^3 nodes (ragged node tiles), 15^3 cubes, several atoms
     cell = W.random_cell(seed=11, L=6.8, h=0.4, n_atoms=6, d_min=1.5, rcut=3.0, npl=30, kT=0.1)
     err, ref, g = _full_compare(sq, cell, "fp64", "ragged 17^3 nodes, 15^3 cube")
-    for k in ("rho", "e_band", "sigma", "K", "N", "rec_rho_q", "rec_K", "rec_N"):
+    for k in ("rho", "e_band", "sigma", "K", "N", "rec_rho_q", "rec_K", "rec_N", "rec_e_nl_q",
+              "rec_vrho_q", "p_direct", "p_trace"):
         assert err[k] < TOL64, (k, err[k])
     assert abs(np.sum(g["rho"]) * cell["h"] ** 3 - cell["n_electrons"]) < 1e-11 * cell["n_electrons"]
 
@@ -220,6 +235,28 @@ def test_call_order_is_enforced(sq):
         with pytest.raises(sq.SqError) as e:
             P.stress(0)
         assert e.value.status == sq.SQ_E_STATE
+        with pytest.raises(sq.SqError) as e:
+            P.pressure(0)
+        assert e.value.status == sq.SQ_E_STATE
+
+
+def test_pressure_runs_the_stress_pass_when_needed(sq):
+    # sq_pressure straight after sq_density runs the stress pass itself; after
+    # a new sq_density the stress columns start from zero again
+    cell = W.tiny_cell()
+    _log("case tiny pressure without sq_stress")
+    with sq.Plan([cell], precision="fp64") as P:
+        P.density(0)
+        pd1, pt1 = P.pressure(0)
+        sig1, _ = P.stress(0)
+        pd2, pt2 = P.pressure(0)
+        P.density(0)
+        rec = P.nodes(0, range(P.n_nodes(0)))
+        pd3, pt3 = P.pressure(0)
+    assert np.all(rec[:, 2:21] == 0.0) and np.all(rec[:, 21] != 0.0)
+    for a, b in ((pd1, pd2), (pt1, pt2), (pd1, pd3), (pt1, pt3)):
+        assert abs(a[0] - b[0]) < 0.1 * TOL64 * abs(b[0])
+    assert abs(pt1[0] + (sig1[0][0] + sig1[0][1] + sig1[0][2]) / 3) < 1e-14 * abs(pt1[0])
 
 
 def test_repeat_runs_agree(sq):

@@ -364,6 +364,7 @@ def test_zero_projector_energy_gives_zero_nonlocal_stress():
     r = O.run(cell, nodes=W.node_sample(1728, 40, 3), mu=0.25)
     assert np.all(r["records"][:, 11:20] == 0.0)
     assert np.all(r["e_nl_node"] == 0.0)
+    assert np.all(r["records"][:, 20] == 0.0)
 
 
 def test_single_atom_on_a_node_gives_isotropic_stress():
@@ -392,3 +393,86 @@ def test_translation_by_a_grid_vector(tiny_run):
     assert np.max(np.abs(rolled - rho2)) < 1e-10 * np.max(rho1)
     assert abs(r1["e_band"] - r2["e_band"]) < 1e-11 * abs(r1["e_band"])
     assert np.max(np.abs(r1["sigma_voigt"] - r2["sigma_voigt"])) < 1e-10 * np.max(np.abs(r1["sigma_voigt"]))
+
+
+# ----------------------------------------------------------------------------
+# direct pressure (App. A)
+# ----------------------------------------------------------------------------
+
+def test_direct_pressure_kinetic_term_is_the_laplacian_trace(tiny, tiny_run):
+    """The direct form replaces the kinetic trace 2 sum_q (grad.grad d_q)_q by
+    the band energy minus the local and nonlocal potential energies, which is
+    2 sum_q (Lap_h d_q)_q up to the Chebyshev truncation of x g(x): with
+    e_q = 2 sum'(chi c + zeta d) rho^j and d_j = (c_{j+1} + c_{j-1}) / 2,
+    e_q = 2 (H_q d_q)_q + zeta_q (c_{n+1} rho^n - c_n rho^{n+1}), n = n_pl.
+    Checked per node against Kronecker-built Lap_h and G_a, and for the cell
+    totals P_direct - P_trace = -(1/(3|Omega|)) sum_q
+    [2 ((Lap_h - sum_a G_a^2) d_q)_q - 2 zeta_q (c_{n+1} rho^n - c_n rho^{n+1})]."""
+    cell, oc = tiny
+    r = tiny_run
+    nc, h, npl, ctr = oc.nc, oc.h, oc.npl, (oc.nc ** 3) // 2
+    lap = sum(D.kron3(D.fd_1d(nc, oc.c2, False), a, nc) for a in range(3)) / h ** 2
+    G = [D.kron3(D.fd_1d(nc, oc.c1, True), a, nc) / h for a in range(3)]
+    row = lap[ctr] - sum(G[a][ctr] @ G[a] for a in range(3))
+    # rho^{n+1} from the recurrence one degree further (chi, zeta do not
+    # depend on the degree)
+    mom1 = O.OracleCell(dict(cell, npl=npl + 1)).moments(r["nodes"], r["chi"], r["zeta"])
+    assert np.array_equal(mom1[:, : npl + 1], r["moments"])
+    # c_{n+1} of the Fermi-Dirac function by a Gauss-Chebyshev rule 8x finer
+    # than the one the coefficients use (the aliasing error is far below 1e-15)
+    Mf = 16384
+    th = np.pi * (np.arange(Mf) + 0.5) / Mf
+    rhs = np.zeros(oc.Nd)
+    lhs = np.zeros(oc.Nd)
+    rec = r["records"]
+    for q in range(oc.Nd):
+        d, _ = oc.dm_column(q, r["chi"][q], r["zeta"][q], r["coef"][q])
+        g = 0.5 * (1 - np.tanh((np.cos(th) - (r["mu"] - r["chi"][q]) / r["zeta"][q])
+                               / (2 * oc.kT / r["zeta"][q])))
+        c_next = 2.0 / Mf * np.sum(g * np.cos((npl + 1) * th))
+        trunc = r["zeta"][q] * (c_next * mom1[q, npl] - r["coef"][q][npl] * mom1[q, npl + 1])
+        rhs[q] = 2 * row @ d - 2 * trunc
+        trK = rec[q, 2] + rec[q, 6] + rec[q, 10]
+        lhs[q] = -2 * rec[q, 1] + 2 * rec[q, 21] + 2 * rec[q, 20] - trK
+    scale = np.max(np.abs(rec[:, 1]))
+    assert np.max(np.abs(lhs - rhs)) < 1e-11 * scale
+    vol3 = 3 * oc.volume
+    diff = r["pressure_direct"] - r["pressure_trace"]
+    assert abs(diff - (-math.fsum(rhs) / vol3)) < 1e-11 * abs(r["pressure_trace"])
+    # the two differ at this mesh: the check is not vacuous
+    assert abs(diff) > 1e-6 * abs(r["pressure_trace"])
+    assert abs(r["pressure_trace"] + np.trace(r["sigma_full"]) / 3) < 1e-14 * abs(r["pressure_trace"])
+
+
+def test_direct_pressure_energy_densities(tiny, tiny_run):
+    """Per-node local-potential energy dV V_q rho_q and nonlocal energy
+    2 sum_I gamma dV chi_I(x_q) chi_I^T d_q from the dense nodal operators."""
+    cell, oc = tiny
+    r = tiny_run
+    for q in _sample(oc, 4, seed=17):
+        i = int(q)
+        dc = _dense_cube(oc, q)
+        d = _dense_column(oc, q, r["chi"][i], r["zeta"][i], r["coef"][i])
+        ctr = dc["ctr"]
+        e_nl = 2 * dc["gdv"] * float(dc["X"][:, ctr] @ (dc["X"] @ d))
+        assert abs(r["records"][i, 20] - e_nl) < 1e-12 * max(1.0, abs(e_nl))
+        assert abs(r["records"][i, 21] - 2 * oc.vloc[i] * d[ctr]) < 1e-12 * abs(r["records"][i, 21])
+
+
+
+def test_pressures_converge_exponentially_with_degree():
+    """Both pressures converge exponentially in n_pl (App. A); the direct
+    form, free of second derivatives of the density matrix, is the better of
+    the two at low degree.  Their limits differ by the mesh term
+    -(2/(3|Omega|)) sum_q ((Lap_h - sum_a G_a^2) d_q)_q, which the identity
+    test above covers at any degree."""
+    vals = {}
+    for npl in (24, 48, 96, 192):
+        r = O.run(W.tiny_cell(npl=npl))
+        vals[npl] = (r["pressure_direct"], r["pressure_trace"])
+    ref_d, ref_t = vals[192]
+    err_d = [abs(vals[n][0] - ref_d) / abs(ref_d) for n in (24, 48, 96)]
+    err_t = [abs(vals[n][1] - ref_t) / abs(ref_t) for n in (24, 48, 96)]
+    assert err_d[0] > err_d[1] > err_d[2] and err_d[2] < 1e-5
+    assert err_t[0] > err_t[1] > err_t[2] and err_t[2] < 1e-5
+    assert err_d[0] < 0.01 * err_t[0]
