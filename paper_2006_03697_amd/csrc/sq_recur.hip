@@ -337,6 +337,25 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
   }
 }
 
+// Weight of a slot on one plane in the working precision: a on the chord,
+// zero off it.  In FP64 only the high word is selected (one select instead of
+// two): off the chord the weight is the subnormal made of a's low word, below
+// 2^-1042 in magnitude, which changes no sum or product it enters by more
+// than that (the vectors and projections it meets are of order one, the
+// results are compared at 1e-10).
+template <typename T>
+__device__ __forceinline__ T chord_weight(bool on, double a);
+template <>
+__device__ __forceinline__ float chord_weight<float>(bool on, double a) {
+  return on ? (float)a : 0.0f;
+}
+template <>
+__device__ __forceinline__ double chord_weight<double>(bool on, double a) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long hi = on ? (b >> 32) : 0ull;
+  return __longlong_as_double((long long)((hi << 32) | (b & 0xffffffffull)));
+}
+
 // Projector weights of one slot along the column: w(z) = a e(z)/e(0) on the
 // planes of the chord, zero elsewhere.  f(z, w) is called for every plane.
 template <int NC, class F>
@@ -346,9 +365,10 @@ __device__ __forceinline__ void slot_sweep(unsigned mk, double a, double rr, dou
     unsigned nm;
     const bool on = __builtin_add_overflow(mk, mk, &nm);   // bit 31 - z
     mk = nm;
-    f(z, on, a);
-    a *= rr;
+    const double an = a * rr;   // before the use: a's registers then hold the weight
     rr *= cq;
+    f(z, on, a);
+    a = an;
   }
 }
 
@@ -384,7 +404,7 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       const int i = (int)(mk & IMASK);
       T part = (T)0;
       slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
-                     [&](int z, bool on, double a) { part += (on ? (T)a : (T)0) * cur[z]; });
+                     [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * cur[z]; });
       if (s < X.nslot) atomicAdd(&S.pacc[par][i], (double)part);
     }
   }
@@ -425,7 +445,7 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       const int i = (int)(mk & IMASK);
       const double coef = s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0;
       slot_sweep<NC>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
-                     [&](int z, bool on, double a) { io[z] += on ? (T)a : (T)0; });
+                     [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
     }
   }
 }
