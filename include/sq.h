@@ -108,7 +108,9 @@ typedef struct {
 } sq_options;
 
 /* Validate the cells, build the per-cell tables (grid, atom images, local
- * potential, per-tile image lists) and allocate the plan's device memory.
+ * potential, per-tile image lists, the Gram matrix of each node's projectors)
+ * and allocate the plan's device memory (about 13 KB per node plus
+ * 8 (2 n_pl + 2 K + 40) bytes per node).
  * Sec. IV: grid K_Omega, cube of side 2 R_cut, atoms of R^3 whose projectors
  * meet the cube.  Returns SQ_E_ARG for a non-integral L/h, R_cut < h,
  * npl outside [1, 256], kT <= 0, an FD order other than 12, or a cube

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sq.h"
@@ -38,6 +39,7 @@ struct CellHost {
 
 struct Group {
   int nc, kc;
+  bool fused;   // the nodes' Gram matrices fit: one sweep per recurrence step
   long long n;
   long long* items;
   int* cell;
@@ -281,16 +283,19 @@ T* upload(sq_plan p, const std::vector<T>& v, sq_status* st) {
   return d;
 }
 
-sq_status make_selection(sq_plan p, const std::vector<int>& cells, Selection& S) {
+// Nodes grouped by (cube width, slot capacity, Gram matrix stored); gn is
+// the per-node Gram entry count (-1: over capacity), or NULL before it is known.
+sq_status make_selection(sq_plan p, const std::vector<int>& cells, Selection& S,
+                         const std::vector<int>* gn = nullptr) {
   S.cells = cells;
-  std::map<std::pair<int, int>, std::vector<std::pair<long long, int>>> by_nc;
+  std::map<std::tuple<int, int, bool>, std::vector<std::pair<long long, int>>> by_nc;
   std::vector<long long> all_items;
   std::vector<int> all_cells;
   for (int ci : cells) {
     const CellHost& c = p->cells[ci];
-    auto& v = by_nc[std::make_pair(c.nc, c.census_col)];
     for (long long q = 0; q < c.Nd; ++q) {
-      v.emplace_back(c.node_base + q, ci);
+      const bool fused = !gn || (*gn)[c.node_base + q] >= 0;
+      by_nc[std::make_tuple(c.nc, c.census_col, fused)].emplace_back(c.node_base + q, ci);
       all_items.push_back(c.node_base + q);
       all_cells.push_back(ci);
     }
@@ -311,8 +316,9 @@ sq_status make_selection(sq_plan p, const std::vector<int>& cells, Selection& S)
       ce.push_back(pr.second);
     }
     Group g;
-    g.nc = kv.first.first;
-    g.kc = kv.first.second;
+    g.nc = std::get<0>(kv.first);
+    g.kc = std::get<1>(kv.first);
+    g.fused = std::get<2>(kv.first);
     g.n = (long long)it.size();
     g.items = upload(p, it, &st);
     g.cell = upload(p, ce, &st);
@@ -421,7 +427,8 @@ sq_status stress_pass(sq_plan p, Selection* S, std::vector<double>& sums) {
   phase_begin(p, PH_STRESS);
   for (const Group& g : S->groups)
     if (st == SQ_OK)
-      st = check_hip(p, sq_launch_stress(g.nc, g.kc, fp64, p->P, g.items, g.cell, g.n, s), "stress");
+      st = check_hip(p, sq_launch_stress(g.nc, g.kc, fp64, g.fused, p->P, g.items, g.cell, g.n, s),
+                     "stress");
   phase_end(p, PH_STRESS);
   phase_begin(p, PH_REDUCE);
   if (st == SQ_OK)
@@ -505,9 +512,12 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   P.mus = (double*)A(sizeof(double) * SQ_MU_STRIDE * n_cells);
   P.sums = (double*)A(sizeof(double) * (SQ_REC + 4) * n_cells);
   P.err = (unsigned*)A(sizeof(unsigned) * 4);
+  P.gval = (double*)A(sizeof(double) * SQ_GRAM_MAX * N);
+  P.gidx = (unsigned*)A(sizeof(unsigned) * SQ_GRAM_MAX * N);
+  P.gn = (int*)A(sizeof(int) * N);
   p->d_cells = (CellDev*)A(sizeof(CellDev) * n_cells);
   if (!P.lan || !P.lan_steps || !P.bnd || !P.mom || !P.coef || !P.rec || !P.nq || !P.mus || !P.sums ||
-      !P.err || !p->d_cells) {
+      !P.err || !P.gval || !P.gidx || !P.gn || !p->d_cells) {
     sq_destroy(p);
     return fail(nullptr, SQ_E_ALLOC, "device allocation failed");
   }
@@ -613,12 +623,23 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
         st = fail(p, SQ_E_ARG, tag + "more than 32 projectors are nonzero at one node");
     }
   }
+  // Gram matrices of every node's projectors (geometry only), then the node
+  // groups, split by whether a node's Gram matrix fits
   if (st == SQ_OK) {
     std::vector<int> all(n_cells);
     for (int i = 0; i < n_cells; ++i) all[i] = i;
-    st = make_selection(p, all, p->all);
+    Selection pre;
+    st = make_selection(p, all, pre);
+    for (const Group& g : pre.groups)
+      if (st == SQ_OK) st = check_hip(p, sq_launch_gram(g.nc, g.kc, P, g.items, g.cell, g.n, p->stream), "gram");
+    std::vector<int> gn(N);
+    if (st == SQ_OK)
+      st = check_hip(p, hipMemcpyAsync(gn.data(), P.gn, sizeof(int) * N, hipMemcpyDeviceToHost, p->stream),
+                     "gram copy");
+    if (st == SQ_OK) st = check_errors(p);
+    if (st == SQ_OK) st = make_selection(p, all, p->all, &gn);
     p->per_cell.resize(n_cells);
-    for (int i = 0; i < n_cells && st == SQ_OK; ++i) st = make_selection(p, {i}, p->per_cell[i]);
+    for (int i = 0; i < n_cells && st == SQ_OK; ++i) st = make_selection(p, {i}, p->per_cell[i], &gn);
   }
   if (st == SQ_OK) {
     st = check_hip(p, hipMemsetAsync(P.rec, 0, sizeof(double) * SQ_REC * N, p->stream), "memset");
@@ -708,7 +729,8 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
   st = check_hip(p, hipMemsetAsync(p->P.err, 0, sizeof(unsigned), s), "memset");
   phase_begin(p, PH_LANCZOS);
   for (const Group& g : S->groups)
-    if (st == SQ_OK) st = check_hip(p, sq_launch_lanczos(g.nc, g.kc, p->P, g.items, g.cell, g.n, s), "lanczos");
+    if (st == SQ_OK)
+      st = check_hip(p, sq_launch_lanczos(g.nc, g.kc, g.fused, p->P, g.items, g.cell, g.n, s), "lanczos");
   phase_end(p, PH_LANCZOS);
   phase_begin(p, PH_BOUNDS);
   if (st == SQ_OK) st = check_hip(p, sq_launch_bounds(p->P, S->items, S->item_cell, S->nall, s), "bounds");
@@ -716,7 +738,8 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
   phase_begin(p, PH_MOMENTS);
   for (const Group& g : S->groups)
     if (st == SQ_OK)
-      st = check_hip(p, sq_launch_moments(g.nc, g.kc, fp64, p->P, g.items, g.cell, g.n, s), "moments");
+      st = check_hip(p, sq_launch_moments(g.nc, g.kc, fp64, g.fused, p->P, g.items, g.cell, g.n, s),
+                     "moments");
   phase_end(p, PH_MOMENTS);
   const int nc = (int)S->cells.size();
   phase_begin(p, PH_MU);

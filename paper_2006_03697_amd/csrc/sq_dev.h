@@ -11,6 +11,7 @@
 #define SQ_KL_MAX 64      // Lanczos steps
 #define SQ_REC 22         // per-node record: rho, e, K[9], N[9], e_nl, dV V rho
 #define SQ_TILE 2         // nodes per tile edge for the image lists
+#define SQ_GRAM_MAX 1024  // projector pairs (I <= J) with overlapping supports in one cube
 
 // error bits raised by kernels
 #define SQ_ERR_SLOTS 1u
@@ -57,6 +58,12 @@ struct PlanDev {
   double* mus;            // [ncell][8] Fermi-level bisection state
   double* sums;           // [ncell][SQ_REC + 4] reduced records
   unsigned* err;          // [1]
+  // Gram matrix of the projectors of each node's cube, upper triangle, pairs
+  // with overlapping supports only (written by the Lanczos pass, read by the
+  // moments and stress passes): value, (I | J << 16), count (-1: too many)
+  double* gval;           // [Ntot][SQ_GRAM_MAX]
+  unsigned* gidx;         // [Ntot][SQ_GRAM_MAX]
+  int* gn;                // [Ntot]
   int mstride;
 };
 
@@ -78,12 +85,16 @@ struct PlanDev {
 extern "C++" {
 // launchers (sq_recur.hip per cube width, sq_misc.hip)
 hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s);
-hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
+// fused: the node's Gram matrix fits (one sweep per step); else two sweeps
+hipError_t sq_launch_lanczos(int nc, int kc, bool fused, const PlanDev& P, const long long* items,
                              const int* item_cell, long long nitems, hipStream_t s);
+hipError_t sq_launch_gram(int nc, int kc, const PlanDev& P, const long long* items,
+                          const int* item_cell, long long nitems, hipStream_t s);
 hipError_t sq_launch_bounds(const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, hipStream_t s);
-hipError_t sq_launch_moments(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
-                             const int* item_cell, long long nitems, hipStream_t s);
+hipError_t sq_launch_moments(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+                             const long long* items, const int* item_cell, long long nitems,
+                             hipStream_t s);
 hipError_t sq_launch_mu_init(const PlanDev& P, const int* cells, int ncells, const int* fixed_mode,
                              hipStream_t s);
 hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int* item_cell,
@@ -91,8 +102,9 @@ hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int
 hipError_t sq_launch_mu_step(const PlanDev& P, const int* cells, int ncells, hipStream_t s);
 hipError_t sq_launch_coeffs(const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, hipStream_t s);
-hipError_t sq_launch_stress(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
-                            const int* item_cell, long long nitems, hipStream_t s);
+hipError_t sq_launch_stress(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+                            const long long* items, const int* item_cell, long long nitems,
+                            hipStream_t s);
 hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, int* stats, long long* pairs, hipStream_t s);
 int sq_kc_limit(bool fp64, int nc);

@@ -87,12 +87,16 @@ __device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
 #define SQ_NC_LIST(X) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25)
 
 #define SQ_DECL_NC(N)                                                                          \
-  hipError_t sq_launch_lanczos_##N(int kc, const PlanDev& P, const long long* items,          \
+  hipError_t sq_launch_lanczos_##N(int kc, bool fused, const PlanDev& P, const long long* items, \
                                    const int* ic, long long n, hipStream_t s);                \
-  hipError_t sq_launch_moments_##N(bool fp64, int kc, const PlanDev& P, const long long* items, \
-                                   const int* ic, long long n, hipStream_t s);                \
-  hipError_t sq_launch_stress_##N(bool fp64, int kc, const PlanDev& P, const long long* items,  \
-                                  const int* ic, long long n, hipStream_t s);                 \
+  hipError_t sq_launch_moments_##N(bool fp64, int kc, bool fused, const PlanDev& P,            \
+                                   const long long* items, const int* ic, long long n,        \
+                                   hipStream_t s);                                            \
+  hipError_t sq_launch_stress_##N(bool fp64, int kc, bool fused, const PlanDev& P,             \
+                                  const long long* items, const int* ic, long long n,         \
+                                  hipStream_t s);                                             \
+  hipError_t sq_launch_gram_##N(int kc, const PlanDev& P, const long long* items, const int* ic, \
+                                long long n, hipStream_t s);                                  \
   hipError_t sq_launch_census_##N(const PlanDev& P, const long long* items, const int* ic,     \
                                   long long n, int* stats, long long* pairs, hipStream_t s);
 SQ_NC_LIST(SQ_DECL_NC)

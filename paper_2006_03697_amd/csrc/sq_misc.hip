@@ -435,30 +435,42 @@ int sq_kc_limit(bool fp64, int nc) { return sq_kc_max(fp64, nc); }
 
 int sq_img_limit(int nc) { return sq_img_max(nc); }
 
-hipError_t sq_launch_lanczos(int nc, int kc, const PlanDev& P, const long long* items,
+hipError_t sq_launch_lanczos(int nc, int kc, bool fused, const PlanDev& P, const long long* items,
                              const int* item_cell, long long nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) if (nc == N) return sq_launch_lanczos_##N(kc, P, items, item_cell, nitems, s);
+#define SQ_CASE(N) \
+  if (nc == N) return sq_launch_lanczos_##N(kc, fused, P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t sq_launch_moments(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
-                             const int* item_cell, long long nitems, hipStream_t s) {
+hipError_t sq_launch_gram(int nc, int kc, const PlanDev& P, const long long* items,
+                          const int* item_cell, long long nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) \
-  if (nc == N) return sq_launch_moments_##N(fp64, kc, P, items, item_cell, nitems, s);
+#define SQ_CASE(N) if (nc == N) return sq_launch_gram_##N(kc, P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t sq_launch_stress(int nc, int kc, bool fp64, const PlanDev& P, const long long* items,
-                            const int* item_cell, long long nitems, hipStream_t s) {
+hipError_t sq_launch_moments(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+                             const long long* items, const int* item_cell, long long nitems,
+                             hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
 #define SQ_CASE(N) \
-  if (nc == N) return sq_launch_stress_##N(fp64, kc, P, items, item_cell, nitems, s);
+  if (nc == N) return sq_launch_moments_##N(fp64, kc, fused, P, items, item_cell, nitems, s);
+  SQ_NC_LIST(SQ_CASE)
+#undef SQ_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t sq_launch_stress(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+                            const long long* items, const int* item_cell, long long nitems,
+                            hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+#define SQ_CASE(N) \
+  if (nc == N) return sq_launch_stress_##N(fp64, kc, fused, P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;

@@ -112,26 +112,39 @@ struct Var {
   static constexpr int IBITS = 32 - NC_;
   static constexpr int NIMG = (1 << IBITS) < 160 ? (1 << IBITS) : 160;
   static constexpr int NEAR = SQ_NEAR_MAX;
-  static constexpr size_t OTHER = 8 * (size_t)NIMG * 11 + (size_t)NEAR * 11 * 8 + NEAR * 4 + 1024;
+  static constexpr size_t OTHER = 8 * (size_t)NIMG * 11 + (size_t)NEAR * 11 * 8 + NEAR * 4 + 1024 +
+                                  12 * (size_t)SQ_GRAM_MAX;
+  // scratch of the Gram build (FP64 Lanczos pass only), in the cube buffer:
+  // pair bitmap [NIMG][NWD], row starts [NIMG + 1], slot words [KC][NT]
+  static constexpr int NWD = (NIMG + 31) / 32;
+  static constexpr size_t GSCR = 4 * ((size_t)NIMG * NWD + NIMG + 1 + (size_t)KC * sq_threads(NC_));
 #ifdef SQ_NO_PAD
   static constexpr bool PAD = false;
 #else
   static constexpr bool PAD = sizeof(T_) * (size_t)Lay<NC_, true>::SIZE + OTHER <= 163840;
 #endif
   using L = Lay<NC_, PAD>;
+  // elements of the cube buffer: the padded or plain cube, or the Gram scratch
+  static constexpr size_t TLN = (sizeof(T_) == 8 && (GSCR + 7) / 8 > (size_t)L::SIZE) ? (GSCR + 7) / 8
+                                                                                   : (size_t)L::SIZE;
 };
 
 template <class Vr>
 struct Smem {
   using T = typename Vr::T;
   static constexpr int NI = Vr::NIMG;
-  T tl[Vr::L::SIZE];
+  T tl[Vr::TLN];
   double ix[NI], iy[NI], iz[NI];      // image positions (unwrapped)
   double rp2[NI], i2s[NI], gdv[NI];   // r_p^2, 1 / (2 sigma_p^2), gamma dV
   // z factor of each image on the cube planes: e(z) = exp(-u_z^2 i2s) with
   // u_z = u_0 + z h, generated as e(z + 1) = e(z) rr(z), rr(z + 1) = rr(z) cq
   double e0[NI], r0[NI], cq[NI];
   double pacc[2][NI];                 // projections, double-buffered over steps
+  // Gram matrix <chi_I, chi_J> over the cube for I <= J with overlapping
+  // supports: value and I | J << 16, ngram entries in (I, J) order
+  double gval[SQ_GRAM_MAX];
+  unsigned gidx[SQ_GRAM_MAX];
+  int ngram;
   double red[2][2 * 16];              // block sums, double-buffered over steps
   double near_chi[Vr::NEAR];
   double nsum[Vr::NEAR][10];
@@ -372,13 +385,45 @@ __device__ __forceinline__ void slot_sweep(unsigned mk, double a, double rr, dou
   }
 }
 
+// Projections <chi_I, v> of the vector v held in registers into S.pacc[buf]
+// (the caller places a barrier before they are read).
+template <class Vr>
+__device__ __forceinline__ void project(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C,
+                                        const typename Vr::T (&v)[Vr::NC], int buf) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
+#pragma unroll
+  for (int s = 0; s < Vr::KC; ++s) {
+    if (s < X.nsw) {
+      const unsigned mk = X.sid[s];
+      const int i = (int)(mk & IMASK);
+      T part = (T)0;
+      slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                     [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
+      if (s < X.nslot) atomicAdd(&S.pacc[buf][i], (double)part);
+    }
+  }
+}
+
 // One application of the nodal operator to the vector held in registers
 // (cur) and mirrored in S.tl:
 //   io <- sc * ((H_q - shift) cur) - pm * io
 // io holds the previous vector on entry and the new one on exit (registers
-// only; the caller mirrors it).  par selects the projection accumulator; the
-// other one is cleared for the next step.  Ends after one block barrier.
-template <class Vr>
+// only; the caller mirrors it).
+//
+// Projections: S.pacc[par] holds <chi_I, cur> on entry and S.pacc[par ^ 1]
+// is zero; on exit S.pacc[par ^ 1] holds <chi_I, io>.  FUSED: they come out
+// of the same sweep that adds the projector terms c_I chi_I, c_I = sc gamma
+// dV <chi_I, cur>: every column visits its images in increasing index, and
+// the projection onto chi_I is taken before the column adds c_I chi_I, so the
+// sweep yields <chi_I, u> + sum_{J < I} c_J G_IJ (u the stencil part of io,
+// G the Gram matrix of the projectors over the cube); the missing
+// sum_{J >= I} G_IJ c_J is added from the stored upper triangle.  Otherwise
+// (a cube whose Gram matrix exceeds its capacity) a second sweep projects
+// the finished io.  The caller clears S.pacc[par] before the next step.
+// Ends after one block barrier.
+template <class Vr, bool FUSED>
 __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
                                            const typename Vr::T (&cur)[Vr::NC],
                                            typename Vr::T (&io)[Vr::NC], const typename Vr::T* ck,
@@ -396,16 +441,13 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
 #pragma unroll
     for (int s = 0; s < Vr::KC; ++s) opaque(X.a0[s]);
   }
-  // (1) projections <chi_I, cur> of every image crossing this column
-#pragma unroll
-  for (int s = 0; s < Vr::KC; ++s) {
-    if (s < nsw) {
-      const unsigned mk = X.sid[s];
-      const int i = (int)(mk & IMASK);
-      T part = (T)0;
-      slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
-                     [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * cur[z]; });
-      if (s < X.nslot) atomicAdd(&S.pacc[par][i], (double)part);
+  if constexpr (FUSED) {
+    // (1) the upper-triangle Gram terms of the new projections
+    const int ngram = S.ngram;
+    for (int e = threadIdx.x; e < ngram; e += L::NT) {
+      const unsigned ij = S.gidx[e];
+      const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+      atomicAdd(&S.pacc[par ^ 1][i], S.gval[e] * (sc * S.gdv[j] * S.pacc[par][j]));
     }
   }
   // (2) stencil + diagonal on the own column (x/y neighbours from LDS)
@@ -435,19 +477,44 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       io[z] = tsc * acc - pm * io[z];
     }
   }
-  for (int i = threadIdx.x; i < Vr::NIMG; i += L::NT) S.pacc[par ^ 1][i] = 0.0;
-  __syncthreads();
-  // (3) the projector terms sc * gamma dV chi_I <chi_I, cur>
+  if constexpr (FUSED) {
+    // (3) one sweep per image: projection of io, then the projector term
 #pragma unroll
-  for (int s = 0; s < Vr::KC; ++s) {
-    if (s < nsw) {
-      const unsigned mk = X.sid[s];
-      const int i = (int)(mk & IMASK);
-      const double coef = s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0;
-      slot_sweep<NC>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
-                     [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
+    for (int s = 0; s < Vr::KC; ++s) {
+      if (s < nsw) {
+        const unsigned mk = X.sid[s];
+        const int i = (int)(mk & IMASK);
+        const T coef = (T)(s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0);
+        T part = (T)0;
+        slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                       [&](int z, bool on, double a) {
+                         const T w = chord_weight<T>(on, a);
+                         part += w * io[z];
+                         io[z] += w * coef;
+                       });
+        if (s < X.nslot) atomicAdd(&S.pacc[par ^ 1][i], (double)part);
+      }
     }
+  } else {
+    // (3') the projector terms, then the projections of the finished io
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) {
+      if (s < nsw) {
+        const unsigned mk = X.sid[s];
+        const int i = (int)(mk & IMASK);
+        const double coef = s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0;
+        slot_sweep<NC>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                       [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
+      }
+    }
+    project<Vr>(S, X, C, io, par ^ 1);
   }
+  __syncthreads();
+}
+
+template <class Vr>
+__device__ __forceinline__ void clear_proj(Smem<Vr>& S, int buf) {
+  for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::L::NT) S.pacc[buf][i] = 0.0;
 }
 
 // Mirror the column into LDS (the caller places a barrier before it is read).
@@ -507,19 +574,160 @@ __device__ __forceinline__ void block_sum2_db(double& a, double& b, double* red)
 }
 
 // ---------------------------------------------------------------------------
+// Gram matrix of the projectors over the cube, G_IJ = <chi_I, chi_J> for
+// I <= J, restricted to the pairs whose chords share a plane on some column
+// (every other entry is zero).  Built once per node by the Lanczos pass from
+// the same per-column chords and weights the sweeps use, and stored for the
+// moments and stress passes.  A cube with more than SQ_GRAM_MAX such pairs
+// gets the count -1, and its steps take two sweeps (projector terms, then
+// projections).  Uses the cube buffer as scratch; the caller clears it
+// afterwards.
+// ---------------------------------------------------------------------------
+template <class Vr>
+__device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C) {
+  using L = typename Vr::L;
+  constexpr int NC = Vr::NC;
+  constexpr int NI = Vr::NIMG;
+  constexpr int NWD = Vr::NWD;
+  constexpr int NT = L::NT;
+  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
+  static_assert(sizeof(S.tl) >= Vr::GSCR, "Gram scratch");
+  unsigned* bm = reinterpret_cast<unsigned*>(S.tl);   // [NI][NWD] pairs present
+  int* rs = reinterpret_cast<int*>(bm + NI * NWD);     // [NI + 1] first entry of each row
+  unsigned* sl = reinterpret_cast<unsigned*>(rs + NI + 1);   // [KC][NT] slot words
+  const int tid = threadIdx.x;
+  for (int k = tid; k < NI * NWD; k += NT) bm[k] = 0u;
+#pragma unroll
+  for (int s = 0; s < Vr::KC; ++s) sl[s * NT + tid] = X.sid[s];
+  __syncthreads();
+  // pairs of this column's slots (image indices increase with the slot)
+  if (X.active) {
+    for (int s = 0; s < X.nslot; ++s) {
+      const unsigned a = sl[s * NT + tid];
+      const int i = (int)(a & IMASK);
+      for (int s2 = s; s2 < X.nslot; ++s2) {
+        const unsigned b = sl[s2 * NT + tid];
+        if ((a & b & ~IMASK) == 0u) continue;
+        const int j = (int)(b & IMASK);
+        atomicOr(&bm[i * NWD + (j >> 5)], 1u << (j & 31));
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < NI) {
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < NWD; ++w) c += __popc(bm[tid * NWD + w]);
+    rs[tid] = c;
+  }
+  __syncthreads();
+  if (tid < 64) {   // exclusive scan of the row counts by wave 0
+    constexpr int PER = (NI + 63) / 64;
+    int loc[PER];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int r = tid * PER + k;
+      loc[k] = r < NI ? rs[r] : 0;
+      sum += loc[k];
+    }
+    int inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o);
+      if (tid >= o) inc += v;
+    }
+    int ex = inc - sum;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int r = tid * PER + k;
+      if (r < NI) rs[r] = ex;
+      ex += loc[k];
+    }
+    if (tid == 63) S.ngram = inc;
+  }
+  __syncthreads();
+  const int total = S.ngram;
+  const bool fits = total <= SQ_GRAM_MAX;
+  if (fits)
+    for (int e = tid; e < total; e += NT) S.gval[e] = 0.0;
+  __syncthreads();
+  // column sums of chi_I chi_J over the shared planes
+  if (X.active && fits) {
+    constexpr int m = NC / 2;
+    const double h = C.h;
+    for (int s = 0; s < X.nslot; ++s) {
+      const unsigned a = sl[s * NT + tid];
+      const int i = (int)(a & IMASK);
+      const double wi = exp(-sq_sum2(node_coord(X.q0 + X.cx - m, h, S.ix[i]),
+                                     node_coord(X.q1 + X.cy - m, h, S.iy[i])) * S.i2s[i]) * S.e0[i];
+      for (int s2 = s; s2 < X.nslot; ++s2) {
+        const unsigned b = sl[s2 * NT + tid];
+        if ((a & b & ~IMASK) == 0u) continue;
+        const int j = (int)(b & IMASK);
+        const double wj = exp(-sq_sum2(node_coord(X.q0 + X.cx - m, h, S.ix[j]),
+                                       node_coord(X.q1 + X.cy - m, h, S.iy[j])) * S.i2s[j]) * S.e0[j];
+        double ai = wi, ri = S.r0[i], aj = wj, rj = S.r0[j], sum = 0.0;
+        const double qi = S.cq[i], qj = S.cq[j];
+        unsigned mk = a & b;
+#pragma unroll
+        for (int z = 0; z < NC; ++z) {
+          unsigned nm;
+          const bool on = __builtin_add_overflow(mk, mk, &nm);
+          mk = nm;
+          sum += on ? ai * aj : 0.0;
+          ai *= ri;
+          ri *= qi;
+          aj *= rj;
+          rj *= qj;
+        }
+        const int jw = j >> 5;
+        int idx = rs[i] + __popc(bm[i * NWD + jw] & ((1u << (j & 31)) - 1u));
+        for (int w = 0; w < jw; ++w) idx += __popc(bm[i * NWD + w]);
+        atomicAdd(&S.gval[idx], sum);
+        S.gidx[idx] = (unsigned)i | ((unsigned)j << 16);
+      }
+    }
+  }
+  if (!fits && tid == 0) S.ngram = -1;   // the steps then take two sweeps
+  __syncthreads();
+}
+
+template <class Vr>
+__device__ __forceinline__ void gram_store(const Smem<Vr>& S, const PlanDev& P, long long g) {
+  const int ng = S.ngram;
+  for (int e = threadIdx.x; e < ng; e += Vr::L::NT) {
+    P.gval[g * SQ_GRAM_MAX + e] = S.gval[e];
+    P.gidx[g * SQ_GRAM_MAX + e] = S.gidx[e];
+  }
+  if (threadIdx.x == 0) P.gn[g] = ng;
+}
+
+// (the caller places a barrier before the entries are read)
+template <class Vr>
+__device__ __forceinline__ void gram_load(Smem<Vr>& S, const PlanDev& P, long long g) {
+  const int ng = min(max(P.gn[g], -1), SQ_GRAM_MAX);
+  for (int e = threadIdx.x; e < ng; e += Vr::L::NT) {
+    S.gval[e] = P.gval[g * SQ_GRAM_MAX + e];
+    S.gidx[e] = P.gidx[g * SQ_GRAM_MAX + e];
+  }
+  if (threadIdx.x == 0) S.ngram = ng;
+}
+
+// ---------------------------------------------------------------------------
 // Spectral bounds: K-step FP64 Lanczos on H_q from the unit vector w_q
 // (chi_q and zeta_q come from the extreme eigenvalues of H_q, Sec. IV)
 // ---------------------------------------------------------------------------
 // One Lanczos step with v_k in A (and S.tl), v_{k-1} in B on entry; on exit
 // v_{k+1} is in B (and S.tl) unless the recursion stopped.
-template <class Vr>
+template <class Vr, bool FUSED>
 __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
                                              const double (&A)[Vr::NC], double (&B)[Vr::NC],
                                              const double* ck, int k, double& bprev, double& tol,
                                              double* lan) {
   constexpr int NC = Vr::NC;
   constexpr int NW = Vr::L::NW;
-  apply_step<Vr>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
+  apply_step<Vr, FUSED>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
   double a = 0.0, dum = 0.0;
 #pragma unroll
   for (int z = 0; z < NC; ++z) a += A[z] * B[z];
@@ -542,12 +750,18 @@ __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const Cell
 #pragma unroll
   for (int z = 0; z < NC; ++z) B[z] *= ib;
   mirror<Vr>(S, X, B);
+  // projections of v_{k+1} = (H v_k - beta v_{k-1} - a v_k) / b
+  const int par = k & 1;
+  for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::L::NT) {
+    S.pacc[par ^ 1][i] = (S.pacc[par ^ 1][i] - a * S.pacc[par][i]) * ib;
+    S.pacc[par][i] = 0.0;
+  }
   bprev = b;
   __syncthreads();
   return true;
 }
 
-template <class Vr>
+template <class Vr, bool FUSED>
 __global__ void __launch_bounds__(Vr::L::NT) k_lanczos(PlanDev P, const long long* items,
                                                         const int* item_cell) {
   static_assert(sizeof(typename Vr::T) == 8, "Lanczos runs in FP64");
@@ -558,21 +772,40 @@ __global__ void __launch_bounds__(Vr::L::NT) k_lanczos(PlanDev P, const long lon
   const long long q = g - C.node_base;
   Ctx<Vr> X;
   node_prologue<Vr>(C, q, 0.0, S, X, P.err);
+  if constexpr (FUSED) gram_load<Vr>(S, P, g);
   double ck[SQ_FDM + 1];
   stencil_coefs<double>(C, ck);
   double A[NC], B[NC];
   load_unit<Vr>(S, X, A, B);
+  project<Vr>(S, X, C, A, 0);
+  __syncthreads();
   double bprev = 0.0, tol = 0.0;
   int steps = 0;
   double* lan = P.lan + g * (2 * SQ_KL_MAX);
   for (int k = 0; k < C.K; k += 2) {
     steps = k + 1;
-    if (!lanczos_step<Vr>(S, X, C, A, B, ck, k, bprev, tol, lan)) break;
+    if (!lanczos_step<Vr, FUSED>(S, X, C, A, B, ck, k, bprev, tol, lan)) break;
     if (k + 1 >= C.K) break;
     steps = k + 2;
-    if (!lanczos_step<Vr>(S, X, C, B, A, ck, k + 1, bprev, tol, lan)) break;
+    if (!lanczos_step<Vr, FUSED>(S, X, C, B, A, ck, k + 1, bprev, tol, lan)) break;
   }
   if (threadIdx.x == 0) P.lan_steps[g] = steps;
+}
+
+// Set-up pass: the Gram matrix of every node's projectors (count -1 when it
+// exceeds SQ_GRAM_MAX entries; such nodes are launched with FUSED = false).
+template <class Vr>
+__global__ void __launch_bounds__(Vr::L::NT) k_gram(PlanDev P, const long long* items,
+                                                     const int* item_cell) {
+  static_assert(sizeof(typename Vr::T) == 8, "the Gram build runs in FP64");
+  __shared__ Smem<Vr> S;
+  const long long g = items[blockIdx.x];
+  const CellDev& C = P.cells[item_cell[blockIdx.x]];
+  const long long q = g - C.node_base;
+  Ctx<Vr> X;
+  node_prologue<Vr>(C, q, 0.0, S, X, P.err);
+  gram_build<Vr>(S, X, C);
+  gram_store<Vr>(S, P, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -581,7 +814,7 @@ __global__ void __launch_bounds__(Vr::L::NT) k_lanczos(PlanDev P, const long lon
 //   rho^{2k} = 2 <t^k, t^k> - rho^0,  rho^{2k+1} = 2 <t^{k+1}, t^k> - rho^1
 // (Hhat_q is symmetric, T_{a+b} + T_{|a-b|} = 2 T_a T_b).
 // ---------------------------------------------------------------------------
-template <class Vr>
+template <class Vr, bool FUSED>
 __global__ void __launch_bounds__(Vr::L::NT) k_moments(PlanDev P, const long long* items,
                                                         const int* item_cell) {
   using T = typename Vr::T;
@@ -594,10 +827,13 @@ __global__ void __launch_bounds__(Vr::L::NT) k_moments(PlanDev P, const long lon
   const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
   Ctx<Vr> X;
   node_prologue<Vr>(C, q, chi, S, X, P.err);
+  if constexpr (FUSED) gram_load<Vr>(S, P, g);
   T ck[SQ_FDM + 1];
   stencil_coefs<T>(C, ck);
   T A[NC], B[NC];
   load_unit<Vr>(S, X, A, B);
+  project<Vr>(S, X, C, A, 0);
+  __syncthreads();
   double* mom = P.mom + g * P.mstride;
   const int npl = C.npl;
   const int kmax = (npl + 1) / 2;
@@ -606,7 +842,7 @@ __global__ void __launch_bounds__(Vr::L::NT) k_moments(PlanDev P, const long lon
   if (threadIdx.x == 0) mom[0] = 1.0;
   // t^{k+1} from t^k (cur) and t^{k-1} (io); then rho^{2k+1}, rho^{2k+2}
   auto step = [&](const T (&cur)[NC], T (&io)[NC], int k) {
-    apply_step<Vr>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, k == 0 ? (T)0 : (T)1,
+    apply_step<Vr, FUSED>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, k == 0 ? (T)0 : (T)1,
                    k & 1);
     double sq = 0.0, cr = 0.0;
 #pragma unroll
@@ -616,6 +852,7 @@ __global__ void __launch_bounds__(Vr::L::NT) k_moments(PlanDev P, const long lon
       cr += a * b;
     }
     mirror<Vr>(S, X, io);
+    clear_proj<Vr>(S, k & 1);
     block_sum2_db<NW>(sq, cr, S.red[k & 1]);
     if (k == 0) rho1 = cr;
     const int j1 = 2 * k + 1, j2 = 2 * k + 2;
@@ -677,7 +914,7 @@ __device__ __forceinline__ void grad_xy_round(Smem<Vr>& S, Ctx<Vr>& X,
   __syncthreads();
 }
 
-template <class Vr>
+template <class Vr, bool FUSED>
 __global__ void __launch_bounds__(Vr::L::NT) k_stress(PlanDev P, const long long* items,
                                                        const int* item_cell) {
   using T = typename Vr::T;
@@ -694,22 +931,26 @@ __global__ void __launch_bounds__(Vr::L::NT) k_stress(PlanDev P, const long long
   const double* coef = P.coef + g * P.mstride;
   Ctx<Vr> X;
   node_prologue<Vr>(C, q, chi, S, X, P.err);
+  if constexpr (FUSED) gram_load<Vr>(S, P, g);
   T ck[SQ_FDM + 1];
   stencil_coefs<T>(C, ck);
   T A[NC], B[NC];
   load_unit<Vr>(S, X, A, B);
+  project<Vr>(S, X, C, A, 0);
+  __syncthreads();
   double d[NC];
   const double c0h = 0.5 * coef[0];
 #pragma unroll
   for (int z = 0; z < NC; ++z) d[z] = c0h * (double)A[z];
   const int npl = C.npl;
   auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
-    apply_step<Vr>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta, j == 0 ? (T)0 : (T)1,
+    apply_step<Vr, FUSED>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta, j == 0 ? (T)0 : (T)1,
                    j & 1);
     const double cj = coef[j + 1];
 #pragma unroll
     for (int z = 0; z < NC; ++z) d[z] += cj * (double)io[z];
     mirror<Vr>(S, X, io);
+    clear_proj<Vr>(S, j & 1);
     __syncthreads();
   };
   for (int j = 0; j < npl; j += 2) {
@@ -950,57 +1191,72 @@ __global__ void __launch_bounds__(sq_threads(NC)) k_census(PlanDev P, const long
 namespace {
 constexpr int SQN = SQ_ONE_NC;
 
-enum Fam { FAM_LAN, FAM_MOM, FAM_STR };
+enum Fam { FAM_LAN, FAM_MOM, FAM_STR, FAM_GRAM };
 
-template <class Vr, int F>
+template <class Vr, int F, bool FUSED>
 hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, long long n,
                       hipStream_t s) {
   const dim3 grid((unsigned)n), block(Vr::L::NT);
   if constexpr (F == FAM_LAN)
-    hipLaunchKernelGGL(k_lanczos<Vr>, grid, block, 0, s, P, items, ic);
+    hipLaunchKernelGGL((k_lanczos<Vr, FUSED>), grid, block, 0, s, P, items, ic);
   else if constexpr (F == FAM_MOM)
-    hipLaunchKernelGGL(k_moments<Vr>, grid, block, 0, s, P, items, ic);
+    hipLaunchKernelGGL((k_moments<Vr, FUSED>), grid, block, 0, s, P, items, ic);
+  else if constexpr (F == FAM_STR)
+    hipLaunchKernelGGL((k_stress<Vr, FUSED>), grid, block, 0, s, P, items, ic);
   else
-    hipLaunchKernelGGL(k_stress<Vr>, grid, block, 0, s, P, items, ic);
+    hipLaunchKernelGGL(k_gram<Vr>, grid, block, 0, s, P, items, ic);
   return hipGetLastError();
 }
 
-template <int F>
+template <int F, bool FUSED>
 hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
                        hipStream_t s) {
-  if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F>(P, items, ic, n, s);
-  if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F>(P, items, ic, n, s);
-  if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F>(P, items, ic, n, s);
+  if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
+  if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F, FUSED>(P, items, ic, n, s);
+  if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  return hipErrorInvalidValue;
+}
+
+template <int F, bool FUSED>
+hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
+                       hipStream_t s) {
+  if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
+  if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F, FUSED>(P, items, ic, n, s);
+  if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
   return hipErrorInvalidValue;
 }
 
 template <int F>
-hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
-                       hipStream_t s) {
-  if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F>(P, items, ic, n, s);
-  if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F>(P, items, ic, n, s);
-  if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F>(P, items, ic, n, s);
-  return hipErrorInvalidValue;
+hipError_t launch_prec(bool fp64, bool fused, int kc, const PlanDev& P, const long long* items,
+                       const int* ic, long long n, hipStream_t s) {
+  if (fp64)
+    return fused ? launch_fp64<F, true>(kc, P, items, ic, n, s) : launch_fp64<F, false>(kc, P, items, ic, n, s);
+  return fused ? launch_fp32<F, true>(kc, P, items, ic, n, s) : launch_fp32<F, false>(kc, P, items, ic, n, s);
 }
 }  // namespace
 
-hipError_t SQ_CAT(sq_launch_lanczos_, SQ_ONE_NC)(int kc, const PlanDev& P, const long long* items,
-                                                const int* ic, long long n, hipStream_t s) {
-  return launch_fp64<FAM_LAN>(kc, P, items, ic, n, s);
-}
-
-hipError_t SQ_CAT(sq_launch_moments_, SQ_ONE_NC)(bool fp64, int kc, const PlanDev& P,
+hipError_t SQ_CAT(sq_launch_lanczos_, SQ_ONE_NC)(int kc, bool fused, const PlanDev& P,
                                                 const long long* items, const int* ic, long long n,
                                                 hipStream_t s) {
-  return fp64 ? launch_fp64<FAM_MOM>(kc, P, items, ic, n, s)
-              : launch_fp32<FAM_MOM>(kc, P, items, ic, n, s);
+  return fused ? launch_fp64<FAM_LAN, true>(kc, P, items, ic, n, s)
+               : launch_fp64<FAM_LAN, false>(kc, P, items, ic, n, s);
 }
 
-hipError_t SQ_CAT(sq_launch_stress_, SQ_ONE_NC)(bool fp64, int kc, const PlanDev& P,
+hipError_t SQ_CAT(sq_launch_moments_, SQ_ONE_NC)(bool fp64, int kc, bool fused, const PlanDev& P,
+                                                const long long* items, const int* ic, long long n,
+                                                hipStream_t s) {
+  return launch_prec<FAM_MOM>(fp64, fused, kc, P, items, ic, n, s);
+}
+
+hipError_t SQ_CAT(sq_launch_stress_, SQ_ONE_NC)(bool fp64, int kc, bool fused, const PlanDev& P,
                                                const long long* items, const int* ic, long long n,
                                                hipStream_t s) {
-  return fp64 ? launch_fp64<FAM_STR>(kc, P, items, ic, n, s)
-              : launch_fp32<FAM_STR>(kc, P, items, ic, n, s);
+  return launch_prec<FAM_STR>(fp64, fused, kc, P, items, ic, n, s);
+}
+
+hipError_t SQ_CAT(sq_launch_gram_, SQ_ONE_NC)(int kc, const PlanDev& P, const long long* items,
+                                             const int* ic, long long n, hipStream_t s) {
+  return launch_fp64<FAM_GRAM, true>(kc, P, items, ic, n, s);
 }
 
 hipError_t SQ_CAT(sq_launch_census_, SQ_ONE_NC)(const PlanDev& P, const long long* items,

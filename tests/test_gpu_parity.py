@@ -129,6 +129,24 @@ def test_ragged_cell_fp64_every_node(sq):
     assert abs(np.sum(g["rho"]) * cell["h"] ** 3 - cell["n_electrons"]) < 1e-11 * cell["n_electrons"]
 
 
+def test_dense_cell_fp64_every_node(sq):
+    # 13 atoms in a 6 Bohr cube: 900 to 1260 overlapping projector pairs per
+    # cube, so some cubes keep their Gram matrix (one sweep per step) and the
+    # others exceed its capacity (two sweeps per step); up to 28 images cross
+    # one column
+    cell = W.random_cell(seed=21, L=6.0, h=0.5, n_atoms=13, d_min=1.2, rcut=2.0, npl=24, kT=0.1)
+    err, ref, g = _full_compare(sq, cell, "fp64", "dense 12^3 nodes, 13 atoms, 9^3 cube")
+    for k in ("rho", "e_band", "sigma", "K", "N", "rec_rho_q", "rec_e_q", "rec_K", "rec_N",
+              "rec_e_nl_q", "rec_vrho_q", "p_direct", "p_trace"):
+        assert err[k] < TOL64, (k, err[k])
+
+
+def test_dense_cell_mixed(sq):
+    cell = W.random_cell(seed=21, L=6.0, h=0.5, n_atoms=13, d_min=1.2, rcut=2.0, npl=24, kT=0.1)
+    err, ref, g = _full_compare(sq, cell, "mixed", "dense 12^3 nodes, 13 atoms, 9^3 cube")
+    assert err["sigma_abs"] < TOL_MIXED_SIGMA and err["p_abs"] < TOL_MIXED_SIGMA
+
+
 def test_fixed_fermi_level_mode(sq):
     cell = W.tiny_cell(npl=20)
     cell["mu_mode"] = "fixed"
