@@ -109,8 +109,8 @@ typedef struct {
 
 /* Validate the cells, build the per-cell tables (grid, atom images, local
  * potential, per-tile image lists, the Gram matrix of each node's projectors)
- * and allocate the plan's device memory (about 13 KB per node plus
- * 8 (2 n_pl + 2 K + 40) bytes per node).
+ * and allocate the plan's device memory (about 13.5 KB per node plus
+ * 16 (n_pl + 2) bytes per node: 12 KB of it the Gram matrix).
  * Sec. IV: grid K_Omega, cube of side 2 R_cut, atoms of R^3 whose projectors
  * meet the cube.  Returns SQ_E_ARG for a non-integral L/h, R_cut < h,
  * npl outside [1, 256], kT <= 0, an FD order other than 12, or a cube

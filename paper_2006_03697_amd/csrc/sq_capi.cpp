@@ -555,6 +555,8 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
     for (int k = 0; k <= SQ_FDM; ++k) {
       d.c2[k] = c.c2[k];
       d.c1[k] = c.c1[k];
+      d.ck[k] = k == 0 ? 0.0 : -0.5 / (c.h * c.h) * c.c2[k];
+      d.ckf[k] = (float)d.ck[k];
     }
     for (int s = 0; s < (int)c.sp.size(); ++s) {
       d.sp[s].v_amp = c.sp[s].v_amp;

@@ -38,6 +38,9 @@ struct CellDev {
   double h, dV, kT, ne, vol, mu0;
   double L[3];
   double c2[SQ_FDM + 1], c1[SQ_FDM + 1];
+  double ck[SQ_FDM + 1];    // kinetic stencil weights -c2[k] / (2 h^2)
+  float ckf[SQ_FDM + 1];    // the same rounded to FP32
+  float padf;
   SpecDev sp[SQ_MAX_SPECIES];
   const double* vloc;     // [Nd]
   const double* img;      // [nimg][4]: x, y, z (unwrapped), species

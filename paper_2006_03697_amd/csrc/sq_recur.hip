@@ -545,10 +545,9 @@ __device__ __forceinline__ void load_unit(Smem<Vr>& S, Ctx<Vr>& X, typename Vr::
 
 template <typename T>
 __device__ __forceinline__ void stencil_coefs(const CellDev& C, T* ck) {
-  const double s = -0.5 / (C.h * C.h);
-  ck[0] = (T)0;
+  // read from the cell table (uniform: the values stay in scalar registers)
 #pragma unroll
-  for (int k = 1; k <= SQ_FDM; ++k) ck[k] = (T)(s * C.c2[k]);
+  for (int k = 0; k <= SQ_FDM; ++k) ck[k] = sizeof(T) == 8 ? (T)C.ck[k] : (T)C.ckf[k];
 }
 
 // Block sums of two values; red is double-buffered by the caller (the next
@@ -1211,6 +1210,7 @@ hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, l
 template <int F, bool FUSED>
 hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
                        hipStream_t s) {
+  if (kc <= 14) return launch_var<Var<double, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
   if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
   if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F, FUSED>(P, items, ic, n, s);
   if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
@@ -1220,6 +1220,7 @@ hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const i
 template <int F, bool FUSED>
 hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
                        hipStream_t s) {
+  if (kc <= 14) return launch_var<Var<float, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
   if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
   if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F, FUSED>(P, items, ic, n, s);
   if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
