@@ -408,7 +408,7 @@ __device__ __forceinline__ void project(Smem<Vr>& S, const Ctx<Vr>& X, const Cel
 
 // One application of the nodal operator to the vector held in registers
 // (cur) and mirrored in S.tl:
-//   io <- sc * ((H_q - shift) cur) - pm * io
+//   io <- sc * ((H_q - shift) cur) - pm * io + cw w_q
 // io holds the previous vector on entry and the new one on exit (registers
 // only; the caller mirrors it).
 //
@@ -427,7 +427,7 @@ template <class Vr, bool FUSED>
 __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
                                            const typename Vr::T (&cur)[Vr::NC],
                                            typename Vr::T (&io)[Vr::NC], const typename Vr::T* ck,
-                                           double sc, typename Vr::T pm, int par) {
+                                           double sc, typename Vr::T pm, int par, double cw = 0.0) {
   using T = typename Vr::T;
   using L = typename Vr::L;
   constexpr int NC = Vr::NC;
@@ -476,6 +476,9 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       }
       io[z] = tsc * acc - pm * io[z];
     }
+    // optional cw w_q (the unit vector at the node): part of the vector the
+    // projector terms are added to, and of its projections
+    if (X.cx == Vr::NC / 2 && X.cy == Vr::NC / 2) io[Vr::NC / 2] += (T)cw;
   }
   if constexpr (FUSED) {
     // (3) one sweep per image: projection of io, then the projector term
@@ -934,27 +937,62 @@ __global__ void __launch_bounds__(Vr::L::NT) k_stress(PlanDev P, const long long
   T ck[SQ_FDM + 1];
   stencil_coefs<T>(C, ck);
   T A[NC], B[NC];
-  load_unit<Vr>(S, X, A, B);
-  project<Vr>(S, X, C, A, 0);
-  __syncthreads();
   double d[NC];
-  const double c0h = 0.5 * coef[0];
-#pragma unroll
-  for (int z = 0; z < NC; ++z) d[z] = c0h * (double)A[z];
   const int npl = C.npl;
-  auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
-    apply_step<Vr, FUSED>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta, j == 0 ? (T)0 : (T)1,
-                   j & 1);
-    const double cj = coef[j + 1];
+  if constexpr (sizeof(T) == 8) {
+    // FP64: Clenshaw's recurrence for d_q = sum'_j c_j T_j(Hhat) w_q,
+    //   b_k = c_k w + 2 Hhat b_{k+1} - b_{k+2},  k = npl-1 .. 1,
+    //   b_npl = c_npl w,  b_{npl+1} = 0,  d_q = c_0 w / 2 + Hhat b_1 - b_2,
+    // the same npl applications as the forward recurrence but no separate
+    // accumulator for d_q (registers)
+    load_unit<Vr>(S, X, A, B);
+    const T cn = (T)coef[npl];
 #pragma unroll
-    for (int z = 0; z < NC; ++z) d[z] += cj * (double)io[z];
-    mirror<Vr>(S, X, io);
-    clear_proj<Vr>(S, j & 1);
+    for (int z = 0; z < NC; ++z) A[z] *= cn;
+    mirror<Vr>(S, X, A);
     __syncthreads();
-  };
-  for (int j = 0; j < npl; j += 2) {
-    step(A, B, j);
-    if (j + 1 < npl) step(B, A, j + 1);
+    project<Vr>(S, X, C, A, 0);
+    __syncthreads();
+    // step j computes b_k, k = npl - 1 - j, from b_{k+1} (cur) and b_{k+2}
+    // (io); the last one (k = 0) forms d_q
+    auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
+      const int k = npl - 1 - j;
+      apply_step<Vr, FUSED>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, (T)1, j & 1,
+                            k == 0 ? 0.5 * coef[0] : coef[k]);
+      mirror<Vr>(S, X, io);
+      clear_proj<Vr>(S, j & 1);
+      __syncthreads();
+    };
+    for (int j = 0; j < npl; j += 2) {
+      step(A, B, j);
+      if (j + 1 < npl) step(B, A, j + 1);
+    }
+    const bool in_b = (npl & 1) != 0;
+#pragma unroll
+    for (int z = 0; z < NC; ++z) d[z] = (double)(in_b ? B[z] : A[z]);
+  } else {
+    // FP32 vectors: forward recurrence t^{j+1} = 2 Hhat t^j - t^{j-1} with
+    // d_q = sum'_j c_j t^j accumulated in FP64
+    load_unit<Vr>(S, X, A, B);
+    project<Vr>(S, X, C, A, 0);
+    __syncthreads();
+    const double c0h = 0.5 * coef[0];
+#pragma unroll
+    for (int z = 0; z < NC; ++z) d[z] = c0h * (double)A[z];
+    auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
+      apply_step<Vr, FUSED>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta,
+                            j == 0 ? (T)0 : (T)1, j & 1);
+      const double cj = coef[j + 1];
+#pragma unroll
+      for (int z = 0; z < NC; ++z) d[z] += cj * (double)io[z];
+      mirror<Vr>(S, X, io);
+      clear_proj<Vr>(S, j & 1);
+      __syncthreads();
+    };
+    for (int j = 0; j < npl; j += 2) {
+      step(A, B, j);
+      if (j + 1 < npl) step(B, A, j + 1);
+    }
   }
 
   // ---- gradients of d along x, y (LDS, FP64 via hi/lo rounds) and z ----
