@@ -39,14 +39,17 @@ F_POINT = 2 * 37 + 2 + 2
 F_PAIR = 4
 
 
-def kernel_flops(info, K):
-    """Algorithmic FLOPs of the three recurrence kernels for one cell."""
+def kernel_flops(info, K, stress_fp64=True):
+    """Algorithmic FLOPs of the three recurrence kernels for one cell.  The
+    FP64 stress pass forms d_q by Clenshaw's recurrence (no per-step
+    accumulation); with FP32 vectors it accumulates d_q += c_j t^j in FP64
+    (2 FLOP per point and step)."""
     Nd, nc, npl, pairs = int(info[0]), int(info[1]), int(info[2]), int(info[8])
     pts = Nd * nc ** 3
     return {
         "lanczos": K * ((F_POINT + 8) * pts + F_PAIR * pairs),
         "moments": ((npl + 1) // 2) * ((F_POINT + 4) * pts + F_PAIR * pairs),
-        "stress": npl * ((F_POINT + 2) * pts + F_PAIR * pairs),
+        "stress": npl * ((F_POINT + (0 if stress_fp64 else 2)) * pts + F_PAIR * pairs),
     }
 
 
@@ -193,7 +196,7 @@ def main():
     r = res[head]
     info = r["info"]
     Nd = int(info[0])
-    flops = kernel_flops(info, K)
+    flops = kernel_flops(info, K, stress_fp64=head == "fp64")
     per_launch = {k: r["phases"][k][0] / max(r["phases"][k][1], 1) for k in flops}
     dom = max(per_launch, key=lambda k: per_launch[k])
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
@@ -230,7 +233,7 @@ def main():
         if mk not in res or head != "fp64":
             continue
         m = res[mk]
-        mf = kernel_flops(m["info"], K)
+        mf = kernel_flops(m["info"], K, stress_fp64=False)
         mpl = {k: m["phases"][k][0] / max(m["phases"][k][1], 1) for k in mf}
         out[mk] = {"value": Nd / (m["ms"] * 1e-3), "ms_per_step": m["ms"], "dtype": "f32+f64",
                    "vectors": "f32 both passes" if mk == "mixed" else "f64 moments, f32 stress pass",
