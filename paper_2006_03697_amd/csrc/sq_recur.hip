@@ -1245,23 +1245,34 @@ hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, l
   return hipGetLastError();
 }
 
+// Nodes without a stored Gram matrix (rare: dense projector overlap) all use
+// the widest slot capacity, so only one two-sweep variant per precision is
+// compiled.
 template <int F, bool FUSED>
 hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
                        hipStream_t s) {
-  if (kc <= 14) return launch_var<Var<double, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
-  if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
-  if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F, FUSED>(P, items, ic, n, s);
-  if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  if constexpr (!FUSED) {
+    if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  } else {
+    if (kc <= 14) return launch_var<Var<double, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
+    if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
+    if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F, FUSED>(P, items, ic, n, s);
+    if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  }
   return hipErrorInvalidValue;
 }
 
 template <int F, bool FUSED>
 hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
                        hipStream_t s) {
-  if (kc <= 14) return launch_var<Var<float, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
-  if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
-  if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F, FUSED>(P, items, ic, n, s);
-  if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  if constexpr (!FUSED) {
+    if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  } else {
+    if (kc <= 14) return launch_var<Var<float, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
+    if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
+    if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F, FUSED>(P, items, ic, n, s);
+    if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+  }
   return hipErrorInvalidValue;
 }
 
