@@ -29,7 +29,10 @@ Readings of what the paper leaves open (also listed in the design notes):
   R3 mu solves 2 sum_q sum' c_q^j(mu) rho_q^j = N_e (bisection on the
      spectral bracket widened by 40 kT on each side), or is fixed;
   R5 d_q^j are the Chebyshev coefficients of r g(r);
-  R8 spherical cutoffs of the Gaussian potential / projector.
+  R8 spherical cutoffs of the Gaussian potential / projector;
+  R16 the direct pressure keeps only the kinetic and nonlocal terms: the
+     kinetic trace from the band energy with the local and nonlocal
+     potential energies taken back out, plus tr N.
 Parity unpinned (problem-definition choices, no external value fixes them):
 the Lanczos step count / widening rule (R1) and the cutoffs (R8).
 """
