@@ -30,6 +30,8 @@ METRIC = "SQ node-columns/sec incl. stress, FP64 vs mixed precision; % HBM roofl
 # FMAs and unpacked FP32 FMAs issue at the same rate (packed FP32 is not used).
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBPS = 8000.0
+# LDS: 128 B per clock per CU
+PEAK_LDS_TBPS = 256 * 128 * 2.4e9 / 1e12
 
 # Algorithmic FLOPs of one application of the scaled nodal operator, per cube
 # node: 37-point 12th-order stencil (37 multiply-adds), local potential
@@ -51,6 +53,16 @@ def kernel_flops(info, K, stress_fp64=True):
         "moments": ((npl + 1) // 2) * ((F_POINT + 4) * pts + F_PAIR * pairs),
         "stress": npl * ((F_POINT + (0 if stress_fp64 else 2)) * pts + F_PAIR * pairs),
     }
+
+
+def lds_bytes(info, K, word):
+    """Algorithmic LDS bytes of the three recurrence kernels for one cell:
+    the 24 in-plane stencil neighbours of every cube point read from the
+    mirror and the point written back, per operator application (word =
+    bytes per vector element)."""
+    Nd, nc, npl = int(info[0]), int(info[1]), int(info[2])
+    per = Nd * nc ** 3 * 25 * word
+    return {"lanczos": K * per, "moments": ((npl + 1) // 2) * per, "stress": npl * per}
 
 
 def hbm_bytes(info, K):
@@ -201,6 +213,9 @@ def main():
     dom = max(per_launch, key=lambda k: per_launch[k])
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
     step_bytes = hbm_bytes(info, K)
+    # bytes per vector element of the dominant kernel in the head precision
+    word = 8 if head == "fp64" or (head == "mixed_stress" and dom != "stress") else 4
+    lds_tbps = lds_bytes(info, K, word)[dom] / (per_launch[dom] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
         "value": Nd / (r["ms"] * 1e-3),
@@ -223,6 +238,8 @@ def main():
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS,
                      "traffic": recorded_traffic(dom, head)},
+        "lds": {"kernel": dom, "achieved": lds_tbps, "peak": PEAK_LDS_TBPS, "unit": "TB/s",
+                "frac": lds_tbps / PEAK_LDS_TBPS},
         "hbm": {"achieved": step_bytes / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": step_bytes / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS},
         "phases_ms": {k: v[0] / max(v[1], 1) for k, v in r["phases"].items()},
