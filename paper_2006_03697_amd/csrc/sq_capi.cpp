@@ -509,6 +509,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   P.coef = (double*)A(sizeof(double) * P.mstride * N);
   P.rec = (double*)A(sizeof(double) * SQ_REC * N);
   P.nq = (double*)A(sizeof(double) * N);
+  P.nqd = (double*)A(sizeof(double) * N);
   P.mus = (double*)A(sizeof(double) * SQ_MU_STRIDE * n_cells);
   P.sums = (double*)A(sizeof(double) * (SQ_REC + 4) * n_cells);
   P.err = (unsigned*)A(sizeof(unsigned) * 4);
@@ -516,7 +517,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   P.gidx = (unsigned*)A(sizeof(unsigned) * SQ_GRAM_MAX * N);
   P.gn = (int*)A(sizeof(int) * N);
   p->d_cells = (CellDev*)A(sizeof(CellDev) * n_cells);
-  if (!P.lan || !P.lan_steps || !P.bnd || !P.mom || !P.coef || !P.rec || !P.nq || !P.mus || !P.sums ||
+  if (!P.lan || !P.lan_steps || !P.bnd || !P.mom || !P.coef || !P.rec || !P.nq || !P.nqd || !P.mus || !P.sums ||
       !P.err || !P.gval || !P.gidx || !P.gn || !p->d_cells) {
     sq_destroy(p);
     return fail(nullptr, SQ_E_ALLOC, "device allocation failed");

@@ -58,6 +58,7 @@ struct PlanDev {
   double* coef;           // [Ntot][mstride]
   double* rec;            // [Ntot][SQ_REC]
   double* nq;             // [Ntot]  per-node electron count at the trial mu
+  double* nqd;            // [Ntot]  its derivative in mu
   double* mus;            // [ncell][8] Fermi-level bisection state
   double* sums;           // [ncell][SQ_REC + 4] reduced records
   unsigned* err;          // [1]

@@ -157,13 +157,14 @@ __global__ void __launch_bounds__(256) k_mu_eval(PlanDev P, const long long* ite
   wave_sync();
   const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
   const Window W = fermi_window(mus[MU_MID], chi, zeta, C.kT, npl);
-  double acc = 0.0;
+  double acc = 0.0, dacc = 0.0;
   // occupied tail: sum'_j rho^j S_j(ka + 1)
   for (int j = lane; j <= npl; j += 64) {
     const double r = j == 0 ? 0.5 * smom[wv][0] : smom[wv][j];
     acc += r * tail_cos_sum(j, W.ka + 1, W.M);
   }
-  // window points: g_k * sum'_j rho^j T_j(x_k) (Clenshaw)
+  // window points: g_k * sum'_j rho^j T_j(x_k) (Clenshaw); the derivative
+  // in mu uses dg/dmu = g (1 - g) / kT, zero on the tails
   for (int k = W.kb + lane; k <= W.ka; k += 64) {
     const double x = cospi(((double)k + 0.5) / (double)W.M);
     const double occ = occupation(x, W);
@@ -175,9 +176,14 @@ __global__ void __launch_bounds__(256) k_mu_eval(PlanDev P, const long long* ite
     }
     const double R = 0.5 * smom[wv][0] + x * b1 - b2;
     acc += occ * R;
+    dacc += occ * (1.0 - occ) * R;
   }
   acc = warp_sum(acc);
-  if (lane == 0) P.nq[g] = (2.0 / (double)W.M) * acc;
+  dacc = warp_sum(dacc);
+  if (lane == 0) {
+    P.nq[g] = (2.0 / (double)W.M) * acc;
+    P.nqd[g] = (2.0 / (double)W.M) * dacc / C.kT;
+  }
 }
 
 // One wave per node: c_j, d_j at the final mu, rho_q and e_q.
@@ -315,21 +321,24 @@ __global__ void __launch_bounds__(256) k_mu_init(PlanDev P, const int* cells, co
 }
 
 // Electron count of each cell at its trial mu and the update of the
-// bracket.  The root of N(mu) = N_e is searched with the Illinois variant of
-// regula falsi (the retained end point's value is halved when the same end
-// is kept twice), with a bisection step whenever four updates have not
-// halved the bracket; it stops at |N - N_e| <= 1e-13 N_e, the criterion of
-// the plain bisection, or after 200 updates.
+// bracket.  The root of N(mu) = N_e is searched inside the bracket by a
+// Newton step from the trial point when it lands inside, else by the
+// Illinois variant of regula falsi (the retained end point's value is halved
+// when the same end is kept twice), with a bisection step whenever four
+// updates have not halved the bracket; it stops at |N - N_e| <= 1e-13 N_e,
+// the criterion of the plain bisection, or after 200 updates.
 __global__ void __launch_bounds__(256) k_mu_step(PlanDev P, const int* cells) {
   __shared__ double rs[256], rc[256];
-  __shared__ double tot;
+  __shared__ double tot, dtot;
   const int ci = cells[blockIdx.x];
   const CellDev& C = P.cells[ci];
   double* m = P.mus + SQ_MU_STRIDE * ci;
   if (m[MU_DONE] != 0.0) return;
   block_neumaier(P.nq + C.node_base, C.Nd, 1, &tot, rs, rc);
+  block_neumaier(P.nqd + C.node_base, C.Nd, 1, &dtot, rs, rc);
   if (threadIdx.x != 0) return;
   const double N = 2.0 * tot;
+  const double dN = 2.0 * dtot;
   const double Ne = C.ne;
   m[MU_N] = N;
   const int phase = (int)m[MU_PHASE];
@@ -377,10 +386,19 @@ __global__ void __launch_bounds__(256) k_mu_step(PlanDev P, const int* cells) {
       return;
     }
   }
-  // next trial point: regula falsi, or bisection if progress stalls
+  // next trial point: Newton from the trial point, else regula falsi, or
+  // bisection if progress stalls
   double x = (lo * fhi - hi * flo) / (fhi - flo);
   const int it = (int)m[MU_IT];
-  if (it > 0 && it % 4 == 0) {
+  bool newton = false;
+  if (phase == 2 && dN > 0.0) {
+    const double xn = mid - (N - Ne) / dN;
+    if (xn > lo && xn < hi) {
+      x = xn;
+      newton = true;
+    }
+  }
+  if (!newton && it > 0 && it % 4 == 0) {
     if (hi - lo > 0.5 * m[MU_WID]) x = 0.5 * (lo + hi);
     m[MU_WID] = hi - lo;
   }

@@ -1,7 +1,8 @@
 // sq_recur.hip -- gfx950 recurrence kernels of the infinite-cell
 // Clenshaw-Curtis SQ hot path (arXiv 2006.03697, Sec. IV and App. A):
-// spectral-bound Lanczos, Chebyshev moments, the stress pass and the
-// capacity census.  Compiled once per cube width NC (SQ_ONE_NC).
+// spectral-bound Lanczos, Chebyshev moments, the stress pass, the projector
+// Gram matrices and the capacity census.  Compiled once per cube width NC
+// (SQ_ONE_NC).
 //
 // One workgroup owns one node q and its cube (region of influence) of
 // NC^3 finite-difference nodes.  Thread (cx, cy) owns the z-column of the
@@ -12,7 +13,9 @@
 // separable Gaussians cut off at a sphere: per (column, image) the chord of
 // the sphere on the column as a bit mask and the projector value at the
 // column's first plane (registers, computed once per node); along the column
-// the Gaussian factor follows from a two-multiply recurrence.
+// the Gaussian factor follows from a two-multiply recurrence.  One sweep per
+// operator application both adds the projector terms and takes the new
+// projections (completed by the stored Gram matrix of the node's projectors).
 #include "sq_devfn.h"
 
 #ifndef SQ_ONE_NC
