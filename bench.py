@@ -4,8 +4,9 @@
 A step is one pass of the whole hot path over one cell already resident in
 HBM: spectral bounds (FP64 Lanczos), Chebyshev moments, Fermi level,
 Clenshaw-Curtis coefficients and density (sq_density), band energy
-(sq_energy), the kinetic + nonlocal stress pass (sq_stress) and the direct
-and trace pressures from its sums (sq_pressure).  The plan
+(sq_energy), the kinetic + nonlocal stress pass (sq_stress), the direct
+and trace pressures from its sums (sq_pressure) and the LDA
+exchange-correlation stress term (sq_xc).  The plan
 (grid, atom images, local potential, capacity census) is built before the
 timed region.  Default workload: the 64000-node cell (16 Bohr cube, h = 0.4,
 64 atoms, 21^3 cubes, degree 60, kT = 0.05 Ha).
@@ -74,7 +75,7 @@ def hbm_bytes(info, K):
     mom = 8 * Nd * (npl + 1) * 2       # moments written, read by coefficients
     coef = 8 * Nd * (npl + 1) * 2      # coefficients written, read by the stress pass
     lan = 8 * Nd * 2 * K               # Lanczos tridiagonals
-    rec = 8 * Nd * 22                  # per-node records
+    rec = 8 * Nd * 24                  # per-node records
     return v + mom + coef + lan + rec
 
 
@@ -125,6 +126,7 @@ def run_precision(sq, cell, precision, steps, warmup):
         plan.energy(0)
         plan.stress(0)
         plan.pressure(0)
+        plan.xc(0)
 
     for _ in range(warmup):
         step()

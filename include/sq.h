@@ -150,11 +150,22 @@ sq_status sq_stress(sq_plan plan, int cell, double* sigma_voigt, double* parts);
  * (SQ_E_STATE otherwise). */
 sq_status sq_pressure(sq_plan plan, int cell, double* p_direct, double* p_trace);
 
-/* Per-node records for a list of nodes of one cell: out [n][22] =
+/* Exchange-correlation energy E_xc = sum_q dV rho_q eps_xc(rho_q) and the
+ * exchange-correlation stress term of Sec. II for a local functional,
+ * delta_ab (E_xc - sum_q dV rho_q v_xc(rho_q)) / |Omega| (isotropic: one
+ * value per cell, the diagonal), from the SQ density.  LDA: Slater exchange
+ * and the Perdew-Wang 1992 correlation of the unpolarised electron gas;
+ * nodes with rho_q <= 0 contribute nothing.  Either output may be NULL.
+ * Needs sq_density (SQ_E_STATE otherwise). */
+sq_status sq_xc(sq_plan plan, int cell, double* e_xc, double* sigma_xc);
+
+/* Per-node records for a list of nodes of one cell: out [n][24] =
  * rho_q, band-energy density e_q, K (9), N (9), nonlocal energy density
  * 2 sum_I gamma dV chi_I(x_q) chi_I^T d_q, local-potential energy
- * dV V_q rho_q.  K, N and the nonlocal energy need the stress pass after the
- * last sq_density (zeros otherwise).  nodes are host arrays. */
+ * dV V_q rho_q, exchange-correlation energy dV rho_q eps_xc and stress
+ * density dV rho_q (eps_xc - v_xc).  K, N and the nonlocal energy need the
+ * stress pass after the last sq_density (zeros otherwise).  nodes are host
+ * arrays. */
 sq_status sq_nodes(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
 /* Per-node spectral bounds lambda_lo, lambda_hi ([N_d] each, host arrays),

@@ -32,7 +32,9 @@ Readings of what the paper leaves open (also listed in the design notes):
   R8 spherical cutoffs of the Gaussian potential / projector;
   R16 the direct pressure keeps only the kinetic and nonlocal terms: the
      kinetic trace from the band energy with the local and nonlocal
-     potential energies taken back out, plus tr N.
+     potential energies taken back out, plus tr N;
+  R17 LDA exchange-correlation: Slater exchange, Perdew-Wang 1992
+     correlation (unpolarised); nodes with rho <= 0 contribute nothing.
 Parity unpinned (problem-definition choices, no external value fixes them):
 the Lanczos step count / widening rule (R1) and the cutoffs (R8).
 """
@@ -393,6 +395,39 @@ def solve_mu(oc: OracleCell, lo_b, hi_b, chi, zeta, mom, n_electrons, tol=1e-13,
     return 0.5 * (lo + hi), max_it
 
 
+# ---------------------------------------------------------------------------
+# LDA exchange-correlation stress (Sec. II, the exchange-correlation term of
+# the stress; for a local functional it is isotropic), reading R17: Slater
+# exchange and the Perdew-Wang 1992 parameterisation of the correlation
+# energy of the unpolarised uniform electron gas
+# ---------------------------------------------------------------------------
+
+def lda_exc(rho):
+    """(eps_xc, v_xc): energy per electron and potential for density rho > 0 (Ha)."""
+    ex, vx, ec, vc = lda_parts(rho)
+    return ex + ec, vx + vc
+
+
+def lda_parts(rho):
+    """(eps_x, v_x, eps_c, v_c) for density rho > 0 (Ha).
+    eps_x = -(3/4) (3 rho / pi)^(1/3); v_x = (4/3) eps_x;
+    eps_c = -2 A (1 + a1 rs) ln(1 + 1 / (2 A (b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2))),
+    rs = (3 / (4 pi rho))^(1/3); v_c = eps_c - (rs / 3) d eps_c / d rs."""
+    rho = np.asarray(rho, dtype=np.float64)
+    ex = -0.75 * np.cbrt(3.0 * rho / np.pi)
+    vx = 4.0 / 3.0 * ex
+    A, a1, b1, b2, b3, b4 = 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294
+    rs = np.cbrt(3.0 / (4.0 * np.pi * rho))
+    srs = np.sqrt(rs)
+    Q0 = -2.0 * A * (1.0 + a1 * rs)
+    Q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs)
+    Q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs)
+    ec = Q0 * np.log(1.0 + 1.0 / Q1)
+    dec = -2.0 * A * a1 * np.log(1.0 + 1.0 / Q1) - Q0 * Q1p / (Q1 * Q1 + Q1)
+    vc = ec - rs / 3.0 * dec
+    return ex, vx, ec, vc
+
+
 def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
     """Full SQ evaluation of one cell.
 
@@ -401,7 +436,9 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
     must be given (a subset cannot fix it).
 
     records[i] = rho_q, band-energy density e_q, K (9), N (9), nonlocal
-    energy density, local-potential energy density dV V_q rho_q.  With the
+    energy density, local-potential energy density dV V_q rho_q, LDA
+    exchange-correlation energy dV rho_q eps_xc and stress density
+    dV rho_q (eps_xc - v_xc).  With the
     stress: sigma = (sum K + sum N) / |Omega| and the pressures
       P_direct = -(-2 E_band + 2 sum_q dV V_q rho_q + 2 E_nl + tr N) / (3 |Omega|)
       P_trace  = -tr(K + N) / (3 |Omega|)."""
@@ -420,7 +457,7 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
             raise ValueError("a node subset needs a given Fermi level")
     c, d = node_coefficients(oc, mu, chi, zeta)
     n = len(nodes)
-    rec = np.zeros((n, 22))
+    rec = np.zeros((n, 24))
     for i in range(n):
         rec[i, 0] = 2.0 / oc.dV * primed(c[i], mom[i])
         rec[i, 1] = 2.0 * primed(chi[i] * c[i] + zeta[i] * d[i], mom[i])
@@ -430,6 +467,18 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
                  volume=oc.volume, dV=oc.dV)
     res["e_band"] = math.fsum(rec[:, 1])
     res["n_count"] = math.fsum(rec[:, 0]) * oc.dV
+    # exchange-correlation energy and the isotropic LDA stress term
+    # sigma^II = delta_ab sum_q dV rho_q (eps_xc - v_xc) / |Omega| (R17)
+    pos = rec[:, 0] > 0.0
+    exc = np.zeros(n)
+    vxc = np.zeros(n)
+    exc[pos], vxc[pos] = lda_exc(rec[pos, 0])
+    xc_e = oc.dV * rec[:, 0] * exc
+    xc_s = oc.dV * rec[:, 0] * (exc - vxc)
+    res["e_xc"] = math.fsum(xc_e)
+    res["sigma_xc"] = math.fsum(xc_s) / oc.volume
+    rec[:, 22] = xc_e
+    rec[:, 23] = xc_s
     if with_stress:
         st = oc.stress_records(nodes, chi, zeta, c)
         rec[:, 2:20] = st[:, 0:18]

@@ -892,6 +892,31 @@ sq_status sq_pressure(sq_plan p, int cell, double* p_direct, double* p_trace) {
   return st;
 }
 
+sq_status sq_xc(sq_plan p, int cell, double* e_xc, double* sigma_xc) {
+  if (!p) return SQ_E_ARG;
+  Selection* S = nullptr;
+  sq_status st = select(p, cell, &S);
+  if (st != SQ_OK) return st;
+  for (int ci : S->cells)
+    if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_xc before sq_density");
+  hipStream_t s = p->stream;
+  phase_begin(p, PH_REDUCE);
+  st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 22, 2, s), "reduce");
+  phase_end(p, PH_REDUCE);
+  std::vector<double> sums;
+  if (st == SQ_OK) st = read_sums(p, sums);
+  phase_collect(p);
+  if (st != SQ_OK) return st;
+  for (size_t i = 0; i < S->cells.size() && st == SQ_OK; ++i) {
+    const int ci = S->cells[i];
+    const double* r = &sums[(SQ_REC + 4) * ci];
+    const double sg = r[23] / p->cells[ci].vol;
+    if (e_xc) st = put_out(p, e_xc + i, &r[22], sizeof(double));
+    if (sigma_xc && st == SQ_OK) st = put_out(p, sigma_xc + i, &sg, sizeof(double));
+  }
+  return st;
+}
+
 sq_status sq_nodes(sq_plan p, int cell, const int64_t* nodes, int64_t n, double* out) {
   if (!p || cell < 0 || cell >= (int)p->cells.size() || (n > 0 && (!nodes || !out))) return SQ_E_ARG;
   if (!p->density_done[cell]) return fail(p, SQ_E_STATE, "sq_nodes before sq_density");

@@ -9,7 +9,7 @@
 #define SQ_MAX_SPECIES 4
 #define SQ_NEAR_MAX 32    // images whose projector is nonzero at the node
 #define SQ_KL_MAX 64      // Lanczos steps
-#define SQ_REC 22         // per-node record: rho, e, K[9], N[9], e_nl, dV V rho
+#define SQ_REC 24         // per-node record: rho, e, K[9], N[9], e_nl, dV V rho, xc energy, xc stress
 #define SQ_TILE 2         // nodes per tile edge for the image lists
 #define SQ_GRAM_MAX 1024  // projector pairs (I <= J) with overlapping supports in one cube
 

@@ -186,6 +186,26 @@ __global__ void __launch_bounds__(256) k_mu_eval(PlanDev P, const long long* ite
   }
 }
 
+// LDA exchange-correlation of the unpolarised uniform electron gas at
+// density r > 0: Slater exchange e_x = -(3/4)(3r/pi)^(1/3), v_x = 4 e_x / 3;
+// Perdew-Wang 1992 correlation with r_s = (3 / (4 pi r))^(1/3),
+// e_c = -2A(1 + a1 r_s) ln(1 + 1/(2A(b1 r_s^1/2 + b2 r_s + b3 r_s^3/2 + b4 r_s^2))),
+// v_c = e_c - (r_s/3) de_c/dr_s.  Returns e_xc and v_xc.
+__device__ void lda_xc(double r, double& exc, double& vxc) {
+  const double ex = -0.75 * cbrt(3.0 * r / M_PI);
+  const double A = 0.031091, a1 = 0.21370, b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double rs = cbrt(3.0 / (4.0 * M_PI * r));
+  const double srs = sqrt(rs);
+  const double q0 = -2.0 * A * (1.0 + a1 * rs);
+  const double q1 = 2.0 * A * srs * (b1 + srs * (b2 + srs * (b3 + b4 * srs)));
+  const double q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
+  const double lg = log1p(1.0 / q1);
+  const double ec = q0 * lg;
+  const double dec = -2.0 * A * a1 * lg - q0 * q1p / (q1 * (q1 + 1.0));
+  exc = ex + ec;
+  vxc = 4.0 / 3.0 * ex + ec - rs / 3.0 * dec;
+}
+
 // One wave per node: c_j, d_j at the final mu, rho_q and e_q.
 __global__ void __launch_bounds__(256) k_coeffs(PlanDev P, const long long* items,
                                                 const int* item_cell, long long nitems) {
@@ -245,13 +265,20 @@ __global__ void __launch_bounds__(256) k_coeffs(PlanDev P, const long long* item
   }
   rs = warp_sum(rs);
   es = warp_sum(es);
-  // rho, band-energy density, local-potential energy dV V_q rho_q; the
-  // stress columns (K, N, nonlocal energy) start at zero until the stress pass
+  // rho, band-energy density, local-potential energy dV V_q rho_q, the LDA
+  // exchange-correlation terms; the stress columns (K, N, nonlocal energy)
+  // start at zero until the stress pass
   double* rec = P.rec + g * SQ_REC;
   if (lane == 0) {
-    rec[0] = 2.0 / C.dV * rs;
+    const double rho = 2.0 / C.dV * rs;
+    rec[0] = rho;
     rec[1] = 2.0 * es;
     rec[21] = 2.0 * C.vloc[g - C.node_base] * rs;
+    // LDA exchange-correlation energy and isotropic stress densities
+    double exc = 0.0, vxc = 0.0;
+    if (rho > 0.0) lda_xc(rho, exc, vxc);
+    rec[22] = C.dV * rho * exc;
+    rec[23] = C.dV * rho * (exc - vxc);
   }
   if (lane >= 2 && lane <= 20) rec[lane] = 0.0;
 }

@@ -21,13 +21,13 @@ SQ_OK, SQ_E_ARG, SQ_E_ALLOC, SQ_E_DEVICE, SQ_E_BOUNDS, SQ_E_NOCONV, SQ_E_STATE =
 SQ_FP64, SQ_MIXED, SQ_MIXED_STRESS = 0, 1, 2
 PRECISIONS = {"fp64": SQ_FP64, "mixed": SQ_MIXED, "mixed_stress": SQ_MIXED_STRESS}
 SQ_MU_SOLVE, SQ_MU_FIXED = 0, 1
-REC = 22
+REC = 24
 
 SPECIES_KEYS = ("v_amp", "v_sigma", "v_rcut", "p_sigma", "p_rcut", "gamma", "z_val")
 
 # Names declared in include/sq.h (kept in step with the header; a CPU test
 # checks both directions).
-EXPORTS = ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_nodes", "sq_bounds",
+EXPORTS = ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
            "sq_moments", "sq_lanczos", "sq_cell_info", "sq_phase_times", "sq_status_str", "sq_last_error",
            "sq_destroy")
 PHASES = ("lanczos", "bounds", "moments", "mu", "coeffs", "stress", "reduce")
@@ -89,6 +89,7 @@ def load():
     L.sq_energy.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     L.sq_stress.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_pressure.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
+    L.sq_xc.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_nodes.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, ctypes.c_int64, dp]
     L.sq_bounds.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_moments.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, ctypes.c_int64, dp]
@@ -101,7 +102,7 @@ def load():
     L.sq_last_error.restype = ctypes.c_char_p
     L.sq_destroy.argtypes = [ctypes.c_void_p]
     L.sq_destroy.restype = None
-    for name in ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_nodes", "sq_bounds",
+    for name in ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
                  "sq_moments", "sq_lanczos", "sq_cell_info", "sq_phase_times"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
@@ -252,6 +253,14 @@ class Plan:
         pt = np.zeros(n)
         self._check(self.L.sq_pressure(self.h, cell, _dp(pd), _dp(pt)), "sq_pressure")
         return pd, pt
+
+    def xc(self, cell: int = -1):
+        """(e_xc, sigma_xc), one value per cell each."""
+        n = len(self._cells(cell))
+        e = np.zeros(n)
+        sg = np.zeros(n)
+        self._check(self.L.sq_xc(self.h, cell, _dp(e), _dp(sg)), "sq_xc")
+        return e, sg
 
     def nodes(self, cell: int, nodes: Iterable[int]) -> np.ndarray:
         nd = np.ascontiguousarray(np.asarray(list(nodes), dtype=np.int64))

@@ -476,3 +476,54 @@ def test_pressures_converge_exponentially_with_degree():
     assert err_d[0] > err_d[1] > err_d[2] and err_d[2] < 1e-5
     assert err_t[0] > err_t[1] > err_t[2] and err_t[2] < 1e-5
     assert err_d[0] < 0.01 * err_t[0]
+
+
+# ----------------------------------------------------------------------------
+# LDA exchange-correlation stress term (reading R17)
+# ----------------------------------------------------------------------------
+
+def test_lda_exchange_is_the_dirac_exchange_of_the_uniform_gas():
+    # eps_x = -3 k_F / (4 pi) with k_F = (3 pi^2 rho)^(1/3)
+    for rho in (1e-3, 0.05, 0.7, 20.0):
+        kf = (3 * math.pi ** 2 * rho) ** (1.0 / 3.0)
+        ex, vx, ec, vc = O.lda_parts(np.array([rho]))
+        assert abs(ex[0] + 3 * kf / (4 * math.pi)) < 1e-14 * kf
+
+
+def test_lda_potential_is_the_density_derivative_of_the_energy_density():
+    # v_xc = d(rho eps_xc)/d rho, checked by Richardson-extrapolated central
+    # differences in log rho
+    for rho in (1e-4, 3e-3, 0.05, 0.7, 20.0):
+        def f(x):
+            e, _ = O.lda_exc(np.array([x]))
+            return x * e[0]
+        def d(hh):
+            return (f(rho * math.exp(hh)) - f(rho * math.exp(-hh))) / (2 * hh) / rho
+        h0 = 1e-3
+        der = (4 * d(h0 / 2) - d(h0)) / 3
+        _, v = O.lda_exc(np.array([rho]))
+        assert abs(v[0] - der) < 1e-9 * abs(v[0])
+
+
+def test_lda_correlation_has_the_high_density_logarithm():
+    # eps_c -> ((1 - ln 2) / pi^2) ln r_s + const for r_s -> 0 (the random-
+    # phase high-density limit)
+    def ec(rs):
+        rho = 3.0 / (4.0 * math.pi * rs ** 3)
+        _, _, e, _ = O.lda_parts(np.array([rho]))
+        return e[0]
+    slope = (ec(1e-6) - ec(1e-8)) / math.log(1e-6 / 1e-8)
+    assert abs(slope - (1 - math.log(2)) / math.pi ** 2) < 1e-4
+
+
+def test_xc_stress_term_of_a_cell(tiny_run):
+    r = tiny_run
+    rho = r["rho"]
+    assert np.all(rho > 0)
+    # isotropic and equal to (E_xc - int v_xc rho) / |Omega|
+    e, v = O.lda_exc(rho)
+    ref = (math.fsum(r["dV"] * rho * e) - math.fsum(r["dV"] * rho * v)) / r["volume"]
+    assert abs(r["sigma_xc"] - ref) < 1e-13 * abs(ref)
+    # for a pure exchange functional (rho^(4/3) energy density) the term is
+    # -E_x / 3 / |Omega|; with correlation the ratio stays near it
+    assert 0.2 < -r["sigma_xc"] * r["volume"] / r["e_xc"] < 0.4
