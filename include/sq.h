@@ -14,7 +14,8 @@
  * d_q = sum' c_q^j t^j, from which the electron density
  * rho_q = (2/dV) sum' c_q^j rho_q^j, the band energy
  * 2 sum_q sum' (chi_q c_q^j + zeta_q d_q^j) rho_q^j, the kinetic and
- * nonlocal density-matrix stress and the pressure follow.
+ * nonlocal density-matrix stress, the pressure and the local
+ * exchange-correlation stress term follow.
  *
  * Units: Hartree atomic units (Ha, Bohr).  All host-side scalars and arrays
  * are IEEE binary64 unless stated otherwise.
