@@ -94,7 +94,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(phase, precision):
+def recorded_traffic(phase, precision, workload="64000-node cell, 21^3 cubes, degree 60"):
     """HBM bytes per launch of a kernel from the profile summaries (a line
     'traffic-json: {...}' with the counters of rocprofv3 --pmc FETCH_SIZE and
     WRITE_SIZE, scaled by the same counters on a plain copy), if they were
@@ -109,7 +109,7 @@ def recorded_traffic(phase, precision):
                 except ValueError:
                     continue
                 if rec.get("phase") == phase and rec.get("precision") == precision and \
-                        rec.get("source_sha1") == want:
+                        rec.get("workload") == workload and rec.get("source_sha1") == want:
                     return float(rec["bytes_per_launch"])
     return None
 
@@ -174,6 +174,9 @@ def main():
                     help="nodes in the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed", "mixed_stress"], default="both",
                     help="both: fp64 (the headline value), mixed and mixed_stress beside it")
+    ap.add_argument("--npl", type=int, default=60,
+                    help="Chebyshev degree of the 64000-node cell (60; the mixed-precision "
+                         "sweep of the same cell uses 40 and 80 as well)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: "
                          "the reference for scaling the HBM byte counters of a profiler")
@@ -197,7 +200,7 @@ def main():
     from paper_2006_03697_amd import sq
     from paper_2006_03697_amd import workloads as W
     sq.load()
-    cell = W.fp64_cell()
+    cell = W.fp64_cell(npl=args.npl)
     K = int(cell["lanczos_steps"])
     res = {}
     for prec in (["fp64", "mixed", "mixed_stress"] if args.precision == "both" else [args.precision]):
@@ -232,14 +235,15 @@ def main():
         "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "periodic 16 Bohr cube, h 0.4 (40^3 = 64000 nodes), 64 atoms "
-                               "(seed 1, min spacing 1.5), R_cut 4 (21^3 cubes), degree 60, "
-                               "kT 0.05 Ha, 12th-order FD, Lanczos K=%d" % K,
+                               "(seed 1, min spacing 1.5), R_cut 4 (21^3 cubes), degree %d, "
+                               "kT 0.05 Ha, 12th-order FD, Lanczos K=%d" % (int(info[2]), K),
                    "nodes": Nd, "cube": int(info[1]) ** 3, "npl": int(info[2]),
                    "precision": head},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS,
-                     "traffic": recorded_traffic(dom, head)},
+                     "traffic": recorded_traffic(dom, head, "64000-node cell, 21^3 cubes, degree %d"
+                                                 % int(info[2]))},
         "lds": {"kernel": dom, "achieved": lds_tbps, "peak": PEAK_LDS_TBPS, "unit": "TB/s",
                 "frac": lds_tbps / PEAK_LDS_TBPS},
         "hbm": {"achieved": step_bytes / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
