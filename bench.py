@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=1536,
+    ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="nodes in the oracle's CPU-baseline sample (0: skip)")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed", "mixed_stress"], default="both",
                     help="both: fp64 (the headline value), mixed and mixed_stress beside it")
