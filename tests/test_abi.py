@@ -82,5 +82,34 @@ def test_per_width_launchers_have_internal_linkage():
            if re.search(r"\s[WVTu]\s", ln) and re.search(r"launch_(fp|var)", ln)]
     assert not bad, bad[:5]
     for n in (7, 9, 11, 13, 15, 17, 19, 21, 23, 25):
-        for fam in ("lanczos", "moments", "stress", "census"):
+        for fam in ("lanczos", "moments", "stress", "gram", "census"):
             assert re.search(r"\sT sq_launch_%s_%d\(" % (fam, n), out), (fam, n)
+
+
+def test_binding_fails_loudly_without_the_library():
+    # no CPU fallback: a missing library is an error at load time
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r); "
+            "from paper_2006_03697_amd import sq\n"
+            "try:\n    sq.load()\nexcept RuntimeError as e:\n    print('raised', e)\n") % ROOT
+    env = dict(os.environ, SQ_LIB_PATH="/nonexistent/libsq_mi355x.so")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert "raised" in out.stdout and "missing" in out.stdout
+
+
+def test_bench_algorithmic_counts():
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    info = [64000, 21, 60, 0, 0, 0, 0, 0, 1000]
+    pts = 64000 * 21 ** 3
+    f = bench.kernel_flops(info, 20)
+    assert f["stress"] == 60 * (78 * pts + 4 * 1000)
+    assert bench.kernel_flops(info, 20, stress_fp64=False)["stress"] == 60 * (80 * pts + 4 * 1000)
+    assert f["moments"] == 30 * (82 * pts + 4 * 1000)
+    assert f["lanczos"] == 20 * (86 * pts + 4 * 1000)
+    assert bench.lds_bytes(info, 20, 8)["stress"] == 60 * pts * 25 * 8
+    # a traffic record is used only for the kernel sources it was taken on
+    assert bench.recorded_traffic("stress", "fp64", "no such workload") is None
