@@ -198,7 +198,7 @@ def test_64000_node_cell_fp64_sampled(sq):
     assert err["lam_lo"] < TOL64 and err["lam_hi"] < TOL64
     assert err["moments"] < TOL64
     assert err["n_count"] < 1e-12
-    for k in ("rho_q", "e_q", "K", "N"):
+    for k in ("rho_q", "e_q", "K", "N", "e_nl_q", "vrho_q", "xc_q"):
         assert err[k] < TOL64, (k, err[k])
 
 
