@@ -99,13 +99,49 @@ typedef struct {
   int lanczos_steps;    /* K of the spectral-bound Lanczos (>= 2; 0 -> 20)  */
 } sq_cell;
 
+/* Plan options.  A zero-initialised struct gives the defaults.
+ *   precision          sq_precision.
+ *   hip_stream         hipStream_t the plan's work is ordered on (NULL: the
+ *                      default stream).
+ *   dev_alloc/dev_free device memory for the plan (NULL: hipMalloc/hipFree).
+ *   outputs_on_device  1: the output pointers of the calls below are device
+ *                      pointers.
+ *   use_graph          1: sq_density and the stress pass capture their launch
+ *                      sequence in a HIP graph on a private stream at their
+ *                      first call for a given cell selection, and replay the
+ *                      graph on hip_stream afterwards (the host only reads
+ *                      back the Fermi level, the error flags and the sums).
+ *   autotune           1: at set-up, time the kernel variants of every
+ *                      node group (slot capacity 16 with the projector
+ *                      weights of plane 0 in registers, or 48 recomputing
+ *                      them; persistent or one-workgroup-per-node launch) on
+ *                      a sample of its nodes and keep the fastest per kernel;
+ *                      0: the smallest capacity and `persistent` below.
+ *   tune_cache         path of a JSON file of tuned choices: read at set-up
+ *                      (a hit skips the timing), rewritten after tuning;
+ *                      NULL: none.  Keys name the device, cube width, slot
+ *                      needs, precision and kernel.
+ *   cheb_quad_points   M_q of the Gauss-Chebyshev rule for the coefficient
+ *                      integrals of Sec. IV (a power of two >= 4 (n_pl + 2));
+ *                      0: the smallest power of two >= max(4 (n_pl + 2),
+ *                      8 zeta_q / kT) per node.
+ *   persistent         0: one workgroup per node; 1: a persistent grid that
+ *                      takes nodes from an atomic work counter (for groups
+ *                      whose columns need at most 16 projector slots).
+ * Node columns of a launch are ordered by decreasing Chebyshev degree
+ * (longest first). */
 typedef struct {
-  int precision;                                  /* sq_precision          */
-  void* hip_stream;                               /* hipStream_t or NULL   */
-  void* (*dev_alloc)(size_t bytes, void* ctx);    /* NULL: hipMalloc       */
+  int precision;
+  void* hip_stream;
+  void* (*dev_alloc)(size_t bytes, void* ctx);
   void (*dev_free)(void* ptr, void* ctx);
   void* alloc_ctx;
-  int outputs_on_device;   /* 1: output pointers below are device pointers */
+  int outputs_on_device;
+  int use_graph;
+  int autotune;
+  const char* tune_cache;
+  int cheb_quad_points;
+  int persistent;
 } sq_options;
 
 /* Validate the cells, build the per-cell tables (grid, atom images, local
@@ -121,8 +157,11 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
 /* Spectral bounds, Chebyshev moments, Fermi level and density (Sec. IV).
  * cell = -1 runs every cell of the plan in the same launches.
  * rho: [N_d] per cell (concatenated in cell order), may be NULL;
- * mu: one per cell, may be NULL.  SQ_E_BOUNDS if a moment left [-1, 1]
- * (tolerance 1e-4), SQ_E_NOCONV if N_e is not bracketed. */
+ * mu: one per cell, may be NULL.  The Fermi level is searched entirely on
+ * the device within a fixed budget of evaluations; the host synchronises
+ * once, at the end.  SQ_E_BOUNDS if a moment left [-1, 1] (tolerance 1e-6
+ * with FP64 moments, 1e-4 with FP32 ones), SQ_E_NOCONV if N_e is not
+ * bracketed or |N - N_e| <= 1e-13 N_e was not reached. */
 sq_status sq_density(sq_plan plan, int cell, double* rho, double* mu);
 
 /* Band energy 2 sum_q sum'_j (chi_q c_q^j + zeta_q d_q^j) rho_q^j (App. A),
@@ -160,7 +199,10 @@ sq_status sq_pressure(sq_plan plan, int cell, double* p_direct, double* p_trace)
  * Needs sq_density (SQ_E_STATE otherwise). */
 sq_status sq_xc(sq_plan plan, int cell, double* e_xc, double* sigma_xc);
 
-/* Per-node records for a list of nodes of one cell: out [n][24] =
+/* Per-node records for a list of nodes of one cell (the per-node terms of
+ * the SQ sums of Sec. IV: the density rho_q = (2/dV) sum' c_q^j rho_q^j, the
+ * node's share of the kinetic and nonlocal stress, and App. A's energy
+ * terms): out [n][24] =
  * rho_q, band-energy density e_q, K (9), N (9), nonlocal energy density
  * 2 sum_I gamma dV chi_I(x_q) chi_I^T d_q, local-potential energy
  * dV V_q rho_q, exchange-correlation energy dV rho_q eps_xc and stress
@@ -169,8 +211,14 @@ sq_status sq_xc(sq_plan plan, int cell, double* e_xc, double* sigma_xc);
  * arrays. */
 sq_status sq_nodes(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
-/* Per-node spectral bounds lambda_lo, lambda_hi ([N_d] each, host arrays),
- * and moments rho_q^j for a list of nodes (out [n][npl+1]). */
+/* Per-node spectral bounds lambda_lo, lambda_hi ([N_d] each, host arrays;
+ * either may be NULL): the interval taken for the extreme eigenvalues
+ * lambda_q^min, lambda_q^max of the nodal Hamiltonian H_q that give
+ * chi_q and zeta_q of Sec. IV (K-step Lanczos from w_q, the extreme Ritz
+ * values widened by their residuals).  sq_moments: the Chebyshev moments
+ * rho_q^j = w_q^T t_q^j of Sec. IV for a list of nodes (out [n][npl+1]).
+ * Both need sq_density (SQ_E_STATE otherwise); SQ_E_ARG for a node index
+ * outside [0, N_d). */
 sq_status sq_bounds(sq_plan plan, int cell, double* lam_lo, double* lam_hi);
 sq_status sq_moments(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
@@ -179,11 +227,12 @@ sq_status sq_moments(sq_plan plan, int cell, const int64_t* nodes, int64_t n, do
  * the steps taken), K = the cell's lanczos_steps.  Needs sq_density. */
 sq_status sq_lanczos(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
-/* Plan queries (info has 9 entries): info[0] = N_d, info[1] = n_c,
+/* Plan queries (info has 10 entries): info[0] = N_d, info[1] = n_c,
  * info[2] = npl, info[3] = number of atom images, info[4] = max images in a
  * node tile, info[5..7] = largest number of images reaching one cube,
  * crossing one cube column, and nonzero at one node, info[8] = number of
- * (node, projector) pairs over all nodes' cubes (measured at set-up). */
+ * (node, projector) pairs over all nodes' cubes (measured at set-up),
+ * info[9] = the Lanczos step count K in effect (lanczos_steps, 0 -> 20). */
 sq_status sq_cell_info(sq_plan plan, int cell, int64_t* info);
 
 /* Device time of each phase accumulated over the calls since the last reset

@@ -25,12 +25,13 @@ EXTRA = os.environ.get("SQ_EXTRA_FLAGS", "").split()
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-HEADERS = [os.path.join(INCLUDE, "sq.h"), os.path.join(CSRC, "sq_dev.h"),
+HEADERS = [os.path.join(INCLUDE, "sq.h"), os.path.join(INCLUDE, "sq_probe.h"), os.path.join(CSRC, "sq_dev.h"),
            os.path.join(CSRC, "sq_devfn.h")]
 
 NC_LIST = [7, 9, 11, 13, 15, 17, 19, 21, 23, 25]
 # (source, device code?, extra defines, object name)
-UNITS = [("sq_misc.hip", True, [], "sq_misc.o"), ("sq_capi.cpp", False, [], "sq_capi.o")] + \
+UNITS = [("sq_misc.hip", True, [], "sq_misc.o"), ("sq_capi.cpp", False, [], "sq_capi.o"),
+         ("sq_probe.hip", True, [], "sq_probe.o")] + \
         [("sq_recur.hip", True, ["-DSQ_ONE_NC=%d" % n], "sq_recur_nc%d.o" % n) for n in NC_LIST]
 
 

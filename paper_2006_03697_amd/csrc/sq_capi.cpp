@@ -1,10 +1,14 @@
 // sq_capi.cpp -- the C ABI (include/sq.h): validation, per-cell tables
-// (grid, atom images, per-tile image lists), device memory, and the order
-// of kernel launches for density, band energy and stress.
+// (grid, atom images, per-tile image lists), device memory, node groups and
+// their tile shapes (fixed or autotuned), and the order of kernel launches
+// for density, band energy and stress, eager or replayed from captured HIP
+// graphs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -28,8 +32,10 @@ struct CellHost {
   int ntile[3];
   std::vector<int> tile_ptr, tile_img;
   int max_tile;
-  int census_img = 0, census_col = 0, census_near = 0;   // measured capacities
-  long long census_pairs = 0;                             // (node, projector) pairs
+  // measured capacities: images per cube, per z-column, nonzero at the
+  // node; (node, projector) pairs
+  int census_img = 0, census_col = 0, census_near = 0;
+  long long census_pairs = 0;
   double c2[SQ_FDM + 1], c1[SQ_FDM + 1];
   double* d_vloc = nullptr;
   double* d_img = nullptr;
@@ -37,22 +43,37 @@ struct CellHost {
   int* d_tile_img = nullptr;
 };
 
+// Variant of one kernel family on a node group.
+struct Tile {
+  int kc = 0;           // slot capacity (16: plane-0 weights in registers, 48: recomputed); 0: smallest
+  int persistent = 0;   // persistent grid with a work counter
+};
+
+enum Fam { F_LAN = 0, F_MOM = 1, F_STR = 2, F_N = 3 };
+
 struct Group {
-  int nc, kc;
-  bool fused;   // the nodes' Gram matrices fit: one sweep per recurrence step
-  long long n;
-  long long* items;
-  int* cell;
+  int nc = 0;
+  bool fused = true;    // the nodes' Gram matrices fit: one sweep per recurrence step
+  int kc1 = 0;          // slot need per z-column (measured)
+  long long n = 0;
+  long long* items = nullptr;   // device, longest first
+  int* cell = nullptr;
+  std::vector<long long> h_items;
+  std::vector<int> h_cell;
+  Tile tile[F_N];
+  unsigned* counter = nullptr;   // work counter of persistent launches
 };
 
 struct Selection {
-  std::vector<Group> groups;   // nodes grouped by cube size
+  std::vector<Group> groups;   // nodes grouped by (cube width, Gram form, slot needs)
   long long nall = 0;
-  long long* items = nullptr;  // every node of the selection
+  long long* items = nullptr;  // every node of the selection, in node order
   int* item_cell = nullptr;
   std::vector<int> cells;
   int* d_cells = nullptr;
   int* d_fixed = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};           // density, stress pass
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -67,7 +88,8 @@ struct sq_plan_s {
   long long phase_n[PH_N] = {};
   sq_options opt{};
   hipStream_t stream = nullptr;
-  int device = 0;
+  hipStream_t cap = nullptr;   // private stream the graphs are captured on
+  bool recording = true;       // phase events are recorded (not while capturing)
   PlanDev P{};
   CellDev* d_cells = nullptr;
   std::vector<void*> allocs;
@@ -76,10 +98,19 @@ struct sq_plan_s {
   std::vector<int> density_done, stress_done;
   long long Ntot = 0;
   std::vector<CellDev> host_cells;   // what was uploaded to d_cells
+  std::map<std::string, Tile> tuned; // autotuned tiles by key
+  std::string arch;
   std::string err;
 };
 
 namespace {
+
+// Fermi-level evaluations launched back to back in every sq_density before
+// the host looks at the search state; a search still running after them
+// continues in rounds of SQ_MU_MORE up to SQ_MU_MAX evaluations.
+constexpr int SQ_MU_BUDGET = 48;
+constexpr int SQ_MU_MORE = 32;
+constexpr int SQ_MU_MAX = 240;
 
 thread_local std::string g_setup_err;
 
@@ -262,6 +293,7 @@ sq_status build_cell(sq_plan p, const sq_cell& in, CellHost& c, int idx) {
   return SQ_OK;
 }
 
+
 template <typename T>
 T* upload(sq_plan p, const std::vector<T>& v, sq_status* st) {
   T* d = (T*)dalloc(p, sizeof(T) * std::max<size_t>(v.size(), 1));
@@ -283,19 +315,61 @@ T* upload(sq_plan p, const std::vector<T>& v, sq_status* st) {
   return d;
 }
 
-// Nodes grouped by (cube width, slot capacity, Gram matrix stored); gn is
-// the per-node Gram entry count (-1: over capacity), or NULL before it is known.
+sq_status check_hip(sq_plan p, hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    return fail(p, SQ_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SQ_OK;
+}
+
+// Key of a tuned tile: device, group shape, precision and kernel family.
+std::string tune_key(sq_plan p, const Group& g, int fam) {
+  const bool fp64 = fam == F_LAN || (fam == F_MOM && p->opt.precision != SQ_MIXED) ||
+                    (fam == F_STR && p->opt.precision == SQ_FP64);
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s|nc=%d|fused=%d|kc=%d|%s|%s", p->arch.c_str(), g.nc,
+                g.fused ? 1 : 0, g.kc1, fp64 ? "fp64" : "fp32",
+                fam == F_LAN ? "lanczos" : (fam == F_MOM ? "moments" : "stress"));
+  return buf;
+}
+
+// A tile serves a group when its slot capacity holds the group's need and
+// the persistent form is compiled for it (16-slot single sweep only).
+bool tile_ok(const Group& g, const Tile& t) {
+  const int kc = t.kc ? t.kc : sq_kc_variant(g.fused, g.kc1);
+  if (kc == 0 || kc < g.kc1 || sq_kc_variant(g.fused, kc) != kc) return false;
+  return !t.persistent || (g.fused && kc == 16);
+}
+
+// Default tile of a group: the smallest slot capacity, the launch form of
+// the options where compiled; a tuned choice overrides both.
+void default_tiles(sq_plan p, Group& g) {
+  for (int f = 0; f < F_N; ++f) {
+    Tile t;
+    t.kc = 0;
+    t.persistent = p->opt.persistent ? 1 : 0;
+    if (!tile_ok(g, t)) t.persistent = 0;
+    auto it = p->tuned.find(tune_key(p, g, f));
+    if (it != p->tuned.end() && tile_ok(g, it->second)) t = it->second;
+    g.tile[f] = t;
+  }
+}
+
+// Nodes grouped by (cube width, Gram matrix stored, slot needs); gn is the
+// per-node Gram entry count (-1: over capacity), or NULL before it is known.
+// Within a group the nodes are ordered longest first (decreasing Chebyshev
+// degree, then node order), so that the last workgroups of a launch are the
+// short ones.
 sq_status make_selection(sq_plan p, const std::vector<int>& cells, Selection& S,
                          const std::vector<int>* gn = nullptr) {
   S.cells = cells;
-  std::map<std::tuple<int, int, bool>, std::vector<std::pair<long long, int>>> by_nc;
+  std::map<std::tuple<int, bool, int>, std::vector<std::pair<long long, int>>> by;
   std::vector<long long> all_items;
   std::vector<int> all_cells;
   for (int ci : cells) {
     const CellHost& c = p->cells[ci];
     for (long long q = 0; q < c.Nd; ++q) {
       const bool fused = !gn || (*gn)[c.node_base + q] >= 0;
-      by_nc[std::make_tuple(c.nc, c.census_col, fused)].emplace_back(c.node_base + q, ci);
+      by[std::make_tuple(c.nc, fused, c.census_col)].emplace_back(c.node_base + q, ci);
       all_items.push_back(c.node_base + q);
       all_cells.push_back(ci);
     }
@@ -308,37 +382,48 @@ sq_status make_selection(sq_plan p, const std::vector<int>& cells, Selection& S,
   for (int ci : cells) fixed.push_back(p->cells[ci].mu_mode == SQ_MU_FIXED ? 1 : 0);
   S.d_cells = upload(p, cells, &st);
   S.d_fixed = upload(p, fixed, &st);
-  for (auto& kv : by_nc) {
-    std::vector<long long> it;
-    std::vector<int> ce;
-    for (auto& pr : kv.second) {
-      it.push_back(pr.first);
-      ce.push_back(pr.second);
-    }
+  for (auto& kv : by) {
+    auto& v = kv.second;
+    std::stable_sort(v.begin(), v.end(), [&](const std::pair<long long, int>& a,
+                                             const std::pair<long long, int>& b) {
+      return p->cells[a.second].npl > p->cells[b.second].npl;
+    });
     Group g;
     g.nc = std::get<0>(kv.first);
-    g.kc = std::get<1>(kv.first);
-    g.fused = std::get<2>(kv.first);
-    g.n = (long long)it.size();
-    g.items = upload(p, it, &st);
-    g.cell = upload(p, ce, &st);
-    S.groups.push_back(g);
+    g.fused = std::get<1>(kv.first);
+    g.kc1 = std::get<2>(kv.first);
+    g.n = (long long)v.size();
+    for (auto& pr : v) {
+      g.h_items.push_back(pr.first);
+      g.h_cell.push_back(pr.second);
+    }
+    g.items = upload(p, g.h_items, &st);
+    g.cell = upload(p, g.h_cell, &st);
+    g.counter = (unsigned*)dalloc(p, sizeof(unsigned));
+    if (!g.counter && st == SQ_OK) st = fail(p, SQ_E_ALLOC, "device allocation failed");
+    default_tiles(p, g);
+    S.groups.push_back(std::move(g));
   }
   return st;
 }
 
-sq_status check_hip(sq_plan p, hipError_t e, const char* what) {
-  if (e != hipSuccess)
-    return fail(p, SQ_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-  return SQ_OK;
+RecLaunch rec_launch(const Group& g, int fam) {
+  const Tile& t = g.tile[fam];
+  RecLaunch R;
+  R.nc = g.nc;
+  R.kc = t.kc ? t.kc : g.kc1;
+  R.fused = g.fused;
+  R.counter = t.persistent ? g.counter : nullptr;
+  R.grid = 0;   // persistent: the launcher sizes the grid to the resident capacity
+  return R;
 }
 
-void phase_begin(sq_plan p, Phase ph) {
-  if (p->ev0[ph] && hipEventRecord(p->ev0[ph], p->stream) == hipSuccess) p->ev_open[ph] = true;
+void phase_begin(sq_plan p, Phase ph, hipStream_t s) {
+  if (p->recording && p->ev0[ph] && hipEventRecord(p->ev0[ph], s) == hipSuccess) p->ev_open[ph] = true;
 }
 
-void phase_end(sq_plan p, Phase ph) {
-  if (p->ev_open[ph]) (void)hipEventRecord(p->ev1[ph], p->stream);
+void phase_end(sq_plan p, Phase ph, hipStream_t s) {
+  if (p->recording && p->ev_open[ph]) (void)hipEventRecord(p->ev1[ph], s);
 }
 
 // After the stream has been synchronised: fold the recorded phases in.
@@ -354,21 +439,16 @@ void phase_collect(sq_plan p) {
   }
 }
 
-// The device copy of the cell table must never change after set-up.
+// The device copy of the cell table must equal the uploaded one (checked
+// once, at the end of set-up).
 sq_status verify_cells(sq_plan p, const char* where) {
   std::vector<CellDev> back(p->host_cells.size());
   hipError_t e = hipMemcpyAsync(back.data(), p->d_cells, sizeof(CellDev) * back.size(),
                                 hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return check_hip(p, e, where);
-  if (std::memcmp(back.data(), p->host_cells.data(), sizeof(CellDev) * back.size()) != 0) {
-    const unsigned char* a = (const unsigned char*)back.data();
-    const unsigned char* b = (const unsigned char*)p->host_cells.data();
-    size_t off = 0;
-    while (off < sizeof(CellDev) * back.size() && a[off] == b[off]) ++off;
-    return fail(p, SQ_E_DEVICE, std::string(where) + ": device cell table differs from the uploaded one at byte " +
-                                    std::to_string(off));
-  }
+  if (std::memcmp(back.data(), p->host_cells.data(), sizeof(CellDev) * back.size()) != 0)
+    return fail(p, SQ_E_DEVICE, std::string(where) + ": device cell table differs from the uploaded one");
   return SQ_OK;
 }
 
@@ -382,21 +462,22 @@ sq_status select(sq_plan p, int cell, Selection** S) {
   return SQ_OK;
 }
 
+sq_status error_status(sq_plan p, unsigned h) {
+  if (h & SQ_ERR_IMAGES) return fail(p, SQ_E_ARG, "more atom images reach a cube than supported");
+  if (h & SQ_ERR_SLOTS) return fail(p, SQ_E_ARG, "more atom images cross a cube column than supported");
+  if (h & SQ_ERR_NEAR) return fail(p, SQ_E_ARG, "more projectors are nonzero at one node than supported");
+  if (h & SQ_ERR_RANGE)
+    return fail(p, SQ_E_BOUNDS, "a projection left the range of the fixed-point sums (|<chi, v>| >= 2^20)");
+  if (h & SQ_ERR_BOUNDS) return fail(p, SQ_E_BOUNDS, "a Chebyshev moment left [-1, 1]: spectral bounds too narrow");
+  return SQ_OK;
+}
+
 sq_status check_errors(sq_plan p) {
   unsigned h = 0;
   hipError_t e = hipMemcpyAsync(&h, p->P.err, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return check_hip(p, e, "device");
-  if (h & SQ_ERR_IMAGES) return fail(p, SQ_E_ARG, "more atom images reach a cube than supported");
-  if (h & SQ_ERR_SLOTS) return fail(p, SQ_E_ARG, "more atom images cross a cube column than supported");
-  if (h & SQ_ERR_NEAR) return fail(p, SQ_E_ARG, "more projectors are nonzero at one node than supported");
-  if (h & SQ_ERR_BOUNDS) return fail(p, SQ_E_BOUNDS, "a Chebyshev moment left [-1, 1]: spectral bounds too narrow");
-  return SQ_OK;
-}
-
-sq_status copy_out(sq_plan p, void* dst, const void* src, size_t bytes) {
-  const hipMemcpyKind k = p->opt.outputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  return check_hip(p, hipMemcpyAsync(dst, src, bytes, k, p->stream), "copy");
+  return error_status(p, h);
 }
 
 // Host value(s) to a caller's output buffer (device or host per the options).
@@ -415,30 +496,249 @@ sq_status read_sums(sq_plan p, std::vector<double>& sums) {
   return st;
 }
 
-// The stress pass over a selection: density-matrix columns, their gradients,
-// K and N per node, the nonlocal energy per node, and the node sums of those
-// columns.  Marks the cells' stress as done.
+// ---- launch sequences (eager on the plan's stream, or captured) -----------
+
+sq_status enqueue_mu_rounds(sq_plan p, Selection* S, int rounds, hipStream_t s) {
+  const int nc = (int)S->cells.size();
+  sq_status st = SQ_OK;
+  for (int k = 0; k < rounds && st == SQ_OK; ++k) {
+    st = check_hip(p, sq_launch_mu_eval(p->P, S->items, S->item_cell, S->nall, s), "mu eval");
+    if (st == SQ_OK) st = check_hip(p, sq_launch_mu_step(p->P, S->d_cells, nc, s), "mu step");
+  }
+  return st;
+}
+
+// Bounds, moments, the Fermi level within its budget, coefficients and
+// density: no host interaction.
+sq_status enqueue_density(sq_plan p, Selection* S, hipStream_t s) {
+  const bool fp64 = p->opt.precision != SQ_MIXED;   // precision of the moments pass
+  sq_status st = check_hip(p, sq_launch_fill_u32(p->P.err, 0u, 1, s), "clear");
+  phase_begin(p, PH_LANCZOS, s);
+  for (const Group& g : S->groups)
+    if (st == SQ_OK)
+      st = check_hip(p, sq_launch_lanczos(rec_launch(g, F_LAN), p->P, g.items, g.cell, g.n, s), "lanczos");
+  phase_end(p, PH_LANCZOS, s);
+  phase_begin(p, PH_BOUNDS, s);
+  if (st == SQ_OK) st = check_hip(p, sq_launch_bounds(p->P, S->items, S->item_cell, S->nall, s), "bounds");
+  phase_end(p, PH_BOUNDS, s);
+  phase_begin(p, PH_MOMENTS, s);
+  for (const Group& g : S->groups)
+    if (st == SQ_OK)
+      st = check_hip(p, sq_launch_moments(rec_launch(g, F_MOM), fp64, p->P, g.items, g.cell, g.n, s),
+                     "moments");
+  phase_end(p, PH_MOMENTS, s);
+  phase_begin(p, PH_MU, s);
+  if (st == SQ_OK)
+    st = check_hip(p, sq_launch_mu_init(p->P, S->d_cells, (int)S->cells.size(), S->d_fixed, s), "mu init");
+  if (st == SQ_OK) st = enqueue_mu_rounds(p, S, SQ_MU_BUDGET, s);
+  phase_end(p, PH_MU, s);
+  phase_begin(p, PH_COEFFS, s);
+  if (st == SQ_OK) st = check_hip(p, sq_launch_coeffs(p->P, S->items, S->item_cell, S->nall, s), "coeffs");
+  phase_end(p, PH_COEFFS, s);
+  return st;
+}
+
+// Density-matrix columns, their gradients, K and N per node, the nonlocal
+// energy per node, and the node sums of those columns.
+sq_status enqueue_stress(sq_plan p, Selection* S, hipStream_t s) {
+  const bool fp64 = p->opt.precision == SQ_FP64;
+  sq_status st = check_hip(p, sq_launch_fill_u32(p->P.err, 0u, 1, s), "clear");
+  phase_begin(p, PH_STRESS, s);
+  for (const Group& g : S->groups)
+    if (st == SQ_OK)
+      st = check_hip(p, sq_launch_stress(rec_launch(g, F_STR), fp64, p->P, g.items, g.cell, g.n, s),
+                     "stress");
+  phase_end(p, PH_STRESS, s);
+  phase_begin(p, PH_REDUCE, s);
+  if (st == SQ_OK)
+    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 2, 19, s), "reduce");
+  phase_end(p, PH_REDUCE, s);
+  return st;
+}
+
+// Runs one of the two sequences: eagerly on the plan's stream, or (use_graph)
+// by replaying its graph, captured on the private stream at the first call.
+sq_status run_sequence(sq_plan p, Selection* S, int which) {
+  auto enq = [&](hipStream_t s) { return which == 0 ? enqueue_density(p, S, s) : enqueue_stress(p, S, s); };
+  if (!p->opt.use_graph) return enq(p->stream);
+  if (!S->exec[which]) {
+    p->recording = false;
+    sq_status st = check_hip(p, hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "capture");
+    if (st == SQ_OK) {
+      const sq_status se = enq(p->cap);
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(p->cap, &graph);
+      st = se != SQ_OK ? se : check_hip(p, ee, "end capture");
+      if (st == SQ_OK && !graph) st = fail(p, SQ_E_DEVICE, "empty graph");
+      if (st == SQ_OK) {
+        hipGraphExec_t exec = nullptr;
+        st = check_hip(p, hipGraphInstantiateWithFlags(&exec, graph, 0), "graph instantiate");
+        if (st == SQ_OK) {
+          S->graph[which] = graph;
+          S->exec[which] = exec;
+        } else {
+          (void)hipGraphDestroy(graph);
+        }
+      } else if (graph) {
+        (void)hipGraphDestroy(graph);
+      }
+    }
+    p->recording = true;
+    if (st != SQ_OK) return st;
+  }
+  return check_hip(p, hipGraphLaunch(S->exec[which], p->stream), "graph launch");
+}
+
+// The stress pass over a selection; marks the cells' stress as done.
 sq_status stress_pass(sq_plan p, Selection* S, std::vector<double>& sums) {
   for (int ci : S->cells)
     if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_stress / sq_pressure before sq_density");
-  const bool fp64 = p->opt.precision == SQ_FP64;
-  hipStream_t s = p->stream;
-  sq_status st = check_hip(p, hipMemsetAsync(p->P.err, 0, sizeof(unsigned), s), "memset");
-  phase_begin(p, PH_STRESS);
-  for (const Group& g : S->groups)
-    if (st == SQ_OK)
-      st = check_hip(p, sq_launch_stress(g.nc, g.kc, fp64, g.fused, p->P, g.items, g.cell, g.n, s),
-                     "stress");
-  phase_end(p, PH_STRESS);
-  phase_begin(p, PH_REDUCE);
-  if (st == SQ_OK)
-    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 2, 19, s), "reduce");
-  phase_end(p, PH_REDUCE);
+  sq_status st = run_sequence(p, S, 1);
   if (st == SQ_OK) st = check_errors(p);
   phase_collect(p);
   if (st == SQ_OK) st = read_sums(p, sums);
   if (st == SQ_OK)
     for (int ci : S->cells) p->stress_done[ci] = 1;
+  return st;
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+// Tiny JSON reader/writer for the tune cache: one object of
+// "key": [slot_capacity, persistent] entries.
+void tune_read(sq_plan p, const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  size_t pos = 0;
+  while ((pos = text.find('"', pos)) != std::string::npos) {
+    const size_t end = text.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = text.substr(pos + 1, end - pos - 1);
+    const size_t lb = text.find('[', end), rb = text.find(']', end);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+    int kc = 0, per = 0;
+    if (std::sscanf(text.c_str() + lb + 1, "%d , %d", &kc, &per) == 2 && (kc == 16 || kc == 48) &&
+        (per == 0 || per == 1)) {
+      Tile t;
+      t.kc = kc;
+      t.persistent = per;
+      p->tuned[key] = t;
+    }
+    pos = rb + 1;
+  }
+}
+
+void tune_write(sq_plan p, const char* path) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : p->tuned)
+    std::fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.kc, kv.second.persistent,
+                 ++i < p->tuned.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+// Device time (ms) of one launch of family fam with tile t on the sample.
+sq_status time_tile(sq_plan p, const Group& g, int fam, const Tile& t, const long long* items,
+                    const int* cells, long long n, float* ms) {
+  Group gg;
+  gg.nc = g.nc;
+  gg.fused = g.fused;
+  gg.kc1 = g.kc1;
+  gg.counter = g.counter;
+  gg.tile[fam] = t;
+  const RecLaunch R = rec_launch(gg, fam);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  sq_status st = check_hip(p, hipEventCreate(&e0), "event");
+  if (st == SQ_OK) st = check_hip(p, hipEventCreate(&e1), "event");
+  float best = 1e30f;
+  for (int rep = 0; rep < 2 && st == SQ_OK; ++rep) {
+    st = check_hip(p, hipEventRecord(e0, p->stream), "event");
+    hipError_t e = hipSuccess;
+    if (fam == F_LAN) e = sq_launch_lanczos(R, p->P, items, cells, n, p->stream);
+    else if (fam == F_MOM) e = sq_launch_moments(R, p->opt.precision != SQ_MIXED, p->P, items, cells, n, p->stream);
+    else e = sq_launch_stress(R, p->opt.precision == SQ_FP64, p->P, items, cells, n, p->stream);
+    if (st == SQ_OK) st = check_hip(p, e, "tune launch");
+    if (st == SQ_OK) st = check_hip(p, hipEventRecord(e1, p->stream), "event");
+    if (st == SQ_OK) st = check_hip(p, hipEventSynchronize(e1), "event");
+    float v = 0.f;
+    if (st == SQ_OK) st = check_hip(p, hipEventElapsedTime(&v, e0, e1), "event");
+    if (st == SQ_OK) best = std::min(best, v);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  *ms = best;
+  return st;
+}
+
+// Picks, per group of the whole-plan selection and kernel family, the
+// fastest variant (slot capacity 16 with the plane-0 weights in registers,
+// or 48 recomputing them; persistent or one workgroup per node) on a sample
+// of the group's nodes (its first nodes: the
+// longest).  The sample's bounds come from the tuned Lanczos, and its
+// coefficients are zero for the stress timing (the operation count does not
+// depend on them).  Every selection's groups then take the choices.
+sq_status autotune(sq_plan p) {
+  sq_status st = SQ_OK;
+  bool dirty = false;
+  for (Group& g : p->all.groups) {
+    bool all_known = true;
+    for (int f = 0; f < F_N; ++f) all_known = all_known && p->tuned.count(tune_key(p, g, f)) > 0;
+    if (all_known) continue;
+    const long long n = std::min<long long>(g.n, 2048);
+    std::vector<Tile> cand;
+    for (int kc : {16, 48})
+      for (int per = 0; per <= 1; ++per) {
+        Tile t;
+        t.kc = kc;
+        t.persistent = per;
+        if (tile_ok(g, t)) cand.push_back(t);
+      }
+    if (cand.size() < 2) continue;   // nothing to choose
+    for (int f = 0; f < F_N && st == SQ_OK; ++f) {
+      if (f == F_STR)
+        st = check_hip(p, sq_launch_fill_u32((unsigned*)p->P.coef, 0u,
+                                             (long long)(2 * p->P.mstride) * p->Ntot, p->stream), "clear");
+      float best = 1e30f;
+      Tile bt = cand[0];
+      for (const Tile& t : cand) {
+        float ms = 0.f;
+        if (st == SQ_OK) st = time_tile(p, g, f, t, g.items, g.cell, n, &ms);
+        if (st == SQ_OK && ms < best) {
+          best = ms;
+          bt = t;
+        }
+      }
+      if (st != SQ_OK) break;
+      p->tuned[tune_key(p, g, f)] = bt;
+      dirty = true;
+      if (f == F_LAN) {   // bounds of the sample for the moments and stress timings
+        Tile keep = g.tile[F_LAN];
+        g.tile[F_LAN] = bt;
+        st = check_hip(p, sq_launch_lanczos(rec_launch(g, F_LAN), p->P, g.items, g.cell, n, p->stream),
+                       "tune lanczos");
+        g.tile[F_LAN] = keep;
+        if (st == SQ_OK) st = check_hip(p, sq_launch_bounds(p->P, g.items, g.cell, n, p->stream), "tune bounds");
+      }
+    }
+  }
+  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(p->stream), "tune");
+  if (st == SQ_OK) st = check_hip(p, sq_launch_fill_u32(p->P.err, 0u, 1, p->stream), "clear");
+  if (st == SQ_OK && dirty && p->opt.tune_cache) tune_write(p, p->opt.tune_cache);
+  if (st == SQ_OK) {
+    for (Group& g : p->all.groups) default_tiles(p, g);
+    for (Selection& S : p->per_cell)
+      for (Group& g : S.groups) default_tiles(p, g);
+  }
   return st;
 }
 
@@ -465,6 +765,17 @@ const char* sq_last_error(sq_plan plan) { return plan ? plan->err.c_str() : g_se
 void sq_destroy(sq_plan plan) {
   if (!plan) return;
   if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+  auto drop = [](Selection& S) {
+    for (int w = 0; w < 2; ++w) {
+      if (S.exec[w]) (void)hipGraphExecDestroy(S.exec[w]);
+      if (S.graph[w]) (void)hipGraphDestroy(S.graph[w]);
+      S.exec[w] = nullptr;
+      S.graph[w] = nullptr;
+    }
+  };
+  drop(plan->all);
+  for (Selection& S : plan->per_cell) drop(S);
+  if (plan->cap) (void)hipStreamDestroy(plan->cap);
   for (int ph = 0; ph < PH_N; ++ph) {
     if (plan->ev0[ph]) (void)hipEventDestroy(plan->ev0[ph]);
     if (plan->ev1[ph]) (void)hipEventDestroy(plan->ev1[ph]);
@@ -482,14 +793,28 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   if (!cells || n_cells < 1 || !opt) return fail(nullptr, SQ_E_ARG, "cells / options missing");
   if (opt->precision != SQ_FP64 && opt->precision != SQ_MIXED && opt->precision != SQ_MIXED_STRESS)
     return fail(nullptr, SQ_E_ARG, "unknown precision");
+  if (opt->cheb_quad_points != 0 &&
+      (opt->cheb_quad_points < 4 || (opt->cheb_quad_points & (opt->cheb_quad_points - 1)) != 0))
+    return fail(nullptr, SQ_E_ARG, "cheb_quad_points must be 0 or a power of two");
   sq_plan p = new sq_plan_s();
   p->opt = *opt;
   p->stream = (hipStream_t)opt->hip_stream;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      p->arch = prop.gcnArchName;
+    const std::string::size_type c = p->arch.find(':');
+    if (c != std::string::npos) p->arch = p->arch.substr(0, c);
+  }
+  if (opt->tune_cache) tune_read(p, opt->tune_cache);
   sq_status st = SQ_OK;
   p->cells.resize(n_cells);
   int npl_max = 1;
   for (int i = 0; i < n_cells; ++i) {
     st = build_cell(p, cells[i], p->cells[i], i);
+    if (st == SQ_OK && opt->cheb_quad_points && opt->cheb_quad_points < 4 * (p->cells[i].npl + 2))
+      st = fail(p, SQ_E_ARG, "cell " + std::to_string(i) + ": cheb_quad_points below 4 (npl + 2)");
     if (st != SQ_OK) {
       sq_destroy(p);
       return st;
@@ -527,7 +852,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   for (int i = 0; i < n_cells && st == SQ_OK; ++i) {
     CellHost& c = p->cells[i];
     c.d_vloc = (double*)A(sizeof(double) * c.Nd);
-    if (!c.d_vloc) st = SQ_E_ALLOC;
+    if (!c.d_vloc) st = fail(p, SQ_E_ALLOC, "device allocation failed");
     if (st == SQ_OK) c.d_img = upload(p, c.img, &st);
     if (st == SQ_OK) c.d_tile_ptr = upload(p, c.tile_ptr, &st);
     if (st == SQ_OK) c.d_tile_img = upload(p, c.tile_img, &st);
@@ -544,6 +869,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
     d.K = c.K;
     d.nimg = (int)(c.img.size() / 4);
     d.nsp = (int)c.sp.size();
+    d.mq = opt->cheb_quad_points;
     d.mu_mode = c.mu_mode;
     d.Nd = c.Nd;
     d.node_base = c.node_base;
@@ -576,25 +902,25 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   if (st == SQ_OK)
     st = check_hip(p, hipMemcpyAsync(p->d_cells, p->host_cells.data(), sizeof(CellDev) * n_cells,
                                      hipMemcpyHostToDevice, p->stream), "upload cells");
-  if (st == SQ_OK) st = verify_cells(p, "after upload");
   for (int i = 0; i < n_cells && st == SQ_OK; ++i)
     st = check_hip(p, sq_launch_vloc(p->d_cells + i, hc[i], p->cells[i].d_vloc, p->stream), "vloc");
-  // capacity census: images per cube, per z-column and at the node itself
+  // capacity census: images per cube, per z-column, per half column and at
+  // the node itself
+  std::vector<int> all(n_cells);
+  for (int i = 0; i < n_cells; ++i) all[i] = i;
   if (st == SQ_OK) {
-    std::vector<int> all(n_cells);
-    for (int i = 0; i < n_cells; ++i) all[i] = i;
     Selection pre;
     st = make_selection(p, all, pre);
-    int* d_stats = (int*)A(sizeof(int) * 4 * n_cells);
+    int* d_stats = (int*)A(sizeof(int) * SQ_CENSUS * n_cells);
     long long* d_pairs = (long long*)A(sizeof(long long) * n_cells);
-    if (!d_stats || !d_pairs) st = SQ_E_ALLOC;
-    if (st == SQ_OK) st = check_hip(p, hipMemsetAsync(d_stats, 0, sizeof(int) * 4 * n_cells, p->stream), "memset");
+    if (st == SQ_OK && (!d_stats || !d_pairs)) st = fail(p, SQ_E_ALLOC, "device allocation failed");
+    if (st == SQ_OK) st = check_hip(p, hipMemsetAsync(d_stats, 0, sizeof(int) * SQ_CENSUS * n_cells, p->stream), "memset");
     if (st == SQ_OK) st = check_hip(p, hipMemsetAsync(d_pairs, 0, sizeof(long long) * n_cells, p->stream), "memset");
     if (st == SQ_OK) st = check_hip(p, hipMemsetAsync(P.err, 0, sizeof(unsigned), p->stream), "memset");
     for (const Group& g : pre.groups)
       if (st == SQ_OK)
         st = check_hip(p, sq_launch_census(g.nc, P, g.items, g.cell, g.n, d_stats, d_pairs, p->stream), "census");
-    std::vector<int> stats(4 * n_cells);
+    std::vector<int> stats(SQ_CENSUS * n_cells);
     std::vector<long long> pairs(n_cells);
     if (st == SQ_OK)
       st = check_hip(p, hipMemcpyAsync(stats.data(), d_stats, sizeof(int) * stats.size(),
@@ -603,16 +929,14 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
       st = check_hip(p, hipMemcpyAsync(pairs.data(), d_pairs, sizeof(long long) * pairs.size(),
                                        hipMemcpyDeviceToHost, p->stream), "census copy");
     if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(p->stream), "census");
-    const bool fp64 = p->opt.precision == SQ_FP64;   // both passes FP64
     for (int i = 0; i < n_cells && st == SQ_OK; ++i) {
       CellHost& c = p->cells[i];
-      c.census_img = stats[4 * i];
-      c.census_col = std::max(1, stats[4 * i + 1]);
-      c.census_near = stats[4 * i + 2];
+      c.census_img = stats[SQ_CENSUS * i];
+      c.census_col = std::max(1, stats[SQ_CENSUS * i + 1]);
+      c.census_near = stats[SQ_CENSUS * i + 2];
       c.census_pairs = pairs[i];
       const std::string tag = "cell " + std::to_string(i) + ": ";
-      // the FP64 Lanczos runs in every precision mode
-      const int kc_lim = std::min(sq_kc_limit(true, c.nc), sq_kc_limit(fp64, c.nc));
+      const int kc_lim = 48;   // widest slot capacity (one thread per column)
       const int img_lim = sq_img_limit(c.nc);
       if (c.census_img > img_lim)
         st = fail(p, SQ_E_ARG, tag + std::to_string(c.census_img) +
@@ -621,7 +945,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
       else if (c.census_col > kc_lim)
         st = fail(p, SQ_E_ARG, tag + std::to_string(c.census_col) +
                                    " atom images cross one cube column (at most " +
-                                   std::to_string(kc_lim) + " supported at this cube width)");
+                                   std::to_string(kc_lim) + " supported)");
       else if (c.census_near > SQ_NEAR_MAX)
         st = fail(p, SQ_E_ARG, tag + "more than 32 projectors are nonzero at one node");
     }
@@ -629,12 +953,10 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   // Gram matrices of every node's projectors (geometry only), then the node
   // groups, split by whether a node's Gram matrix fits
   if (st == SQ_OK) {
-    std::vector<int> all(n_cells);
-    for (int i = 0; i < n_cells; ++i) all[i] = i;
     Selection pre;
     st = make_selection(p, all, pre);
     for (const Group& g : pre.groups)
-      if (st == SQ_OK) st = check_hip(p, sq_launch_gram(g.nc, g.kc, P, g.items, g.cell, g.n, p->stream), "gram");
+      if (st == SQ_OK) st = check_hip(p, sq_launch_gram(g.nc, P, g.items, g.cell, g.n, p->stream), "gram");
     std::vector<int> gn(N);
     if (st == SQ_OK)
       st = check_hip(p, hipMemcpyAsync(gn.data(), P.gn, sizeof(int) * N, hipMemcpyDeviceToHost, p->stream),
@@ -644,6 +966,9 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
     p->per_cell.resize(n_cells);
     for (int i = 0; i < n_cells && st == SQ_OK; ++i) st = make_selection(p, {i}, p->per_cell[i], &gn);
   }
+  if (st == SQ_OK && opt->use_graph)
+    st = check_hip(p, hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking), "capture stream");
+  if (st == SQ_OK && opt->autotune) st = autotune(p);
   if (st == SQ_OK) {
     st = check_hip(p, hipMemsetAsync(P.rec, 0, sizeof(double) * SQ_REC * N, p->stream), "memset");
     if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(p->stream), "setup");
@@ -706,6 +1031,7 @@ sq_status sq_cell_info(sq_plan p, int cell, int64_t* info) {
   info[6] = c.census_col;
   info[7] = c.census_near;
   info[8] = c.census_pairs;
+  info[9] = c.K;
   return SQ_OK;
 }
 
@@ -727,59 +1053,49 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
   if (st != SQ_OK) return st;
-  const bool fp64 = p->opt.precision != SQ_MIXED;   // precision of the moments pass
   hipStream_t s = p->stream;
-  st = check_hip(p, hipMemsetAsync(p->P.err, 0, sizeof(unsigned), s), "memset");
-  phase_begin(p, PH_LANCZOS);
-  for (const Group& g : S->groups)
-    if (st == SQ_OK)
-      st = check_hip(p, sq_launch_lanczos(g.nc, g.kc, g.fused, p->P, g.items, g.cell, g.n, s), "lanczos");
-  phase_end(p, PH_LANCZOS);
-  phase_begin(p, PH_BOUNDS);
-  if (st == SQ_OK) st = check_hip(p, sq_launch_bounds(p->P, S->items, S->item_cell, S->nall, s), "bounds");
-  phase_end(p, PH_BOUNDS);
-  phase_begin(p, PH_MOMENTS);
-  for (const Group& g : S->groups)
-    if (st == SQ_OK)
-      st = check_hip(p, sq_launch_moments(g.nc, g.kc, fp64, g.fused, p->P, g.items, g.cell, g.n, s),
-                     "moments");
-  phase_end(p, PH_MOMENTS);
-  const int nc = (int)S->cells.size();
-  phase_begin(p, PH_MU);
-  if (st == SQ_OK) st = check_hip(p, sq_launch_mu_init(p->P, S->d_cells, nc, S->d_fixed, s), "mu init");
+  st = run_sequence(p, S, 0);
   if (st != SQ_OK) return st;
-  st = check_errors(p);
-  if (st != SQ_OK) return st;
-  // Fermi level: bracketed root search entirely on the device; the host
-  // checks for completion after 10 evaluations, then every 4
+  // one synchronisation: error flags and the search state of every cell
   std::vector<double> mus(SQ_MU_STRIDE * p->cells.size());
-  for (int it = 0, blk = 10; it < 210 && st == SQ_OK; it += blk, blk = 4) {
-    for (int k = 0; k < blk && st == SQ_OK; ++k) {
-      st = check_hip(p, sq_launch_mu_eval(p->P, S->items, S->item_cell, S->nall, s), "mu eval");
-      if (st == SQ_OK) st = check_hip(p, sq_launch_mu_step(p->P, S->d_cells, nc, s), "mu step");
-    }
-    if (st != SQ_OK) break;
-    st = check_hip(p, hipMemcpyAsync(mus.data(), p->P.mus, sizeof(double) * mus.size(),
-                                     hipMemcpyDeviceToHost, s), "mu copy");
-    if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "mu sync");
-    bool done = true;
-    for (int ci : S->cells) done = done && mus[SQ_MU_STRIDE * ci + MU_DONE] != 0.0;
-    if (done) break;
-  }
-  if (st != SQ_OK) return st;
-  for (int ci : S->cells) {
-    if (mus[SQ_MU_STRIDE * ci + MU_DONE] == 2.0)
-      return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": N_e not bracketed");
-    if (mus[SQ_MU_STRIDE * ci + MU_DONE] == 0.0)
-      return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": Fermi-level search did not finish");
-  }
-  phase_end(p, PH_MU);
-  phase_begin(p, PH_COEFFS);
-  st = check_hip(p, sq_launch_coeffs(p->P, S->items, S->item_cell, S->nall, s), "coeffs");
-  phase_end(p, PH_COEFFS);
-  if (st == SQ_OK) st = check_errors(p);
+  unsigned eflags = 0;
+  st = check_hip(p, hipMemcpyAsync(mus.data(), p->P.mus, sizeof(double) * mus.size(),
+                                   hipMemcpyDeviceToHost, s), "mu copy");
+  if (st == SQ_OK)
+    st = check_hip(p, hipMemcpyAsync(&eflags, p->P.err, sizeof(unsigned), hipMemcpyDeviceToHost, s), "flags");
+  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "density");
   phase_collect(p);
   if (st != SQ_OK) return st;
+  st = error_status(p, eflags);
+  if (st != SQ_OK) return st;
+  auto running = [&]() {
+    for (int ci : S->cells)
+      if (mus[SQ_MU_STRIDE * ci + MU_DONE] == 0.0) return true;
+    return false;
+  };
+  // a search still running after the budget: more rounds, then the
+  // coefficients again
+  if (running()) {
+    for (int done_it = SQ_MU_BUDGET; done_it < SQ_MU_MAX && running() && st == SQ_OK; done_it += SQ_MU_MORE) {
+      st = enqueue_mu_rounds(p, S, SQ_MU_MORE, s);
+      if (st == SQ_OK)
+        st = check_hip(p, hipMemcpyAsync(mus.data(), p->P.mus, sizeof(double) * mus.size(),
+                                         hipMemcpyDeviceToHost, s), "mu copy");
+      if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "mu sync");
+    }
+    if (st == SQ_OK && !running())
+      st = check_hip(p, sq_launch_coeffs(p->P, S->items, S->item_cell, S->nall, s), "coeffs");
+    if (st != SQ_OK) return st;
+  }
+  for (int ci : S->cells) {
+    const double d = mus[SQ_MU_STRIDE * ci + MU_DONE];
+    if (d == 2.0) return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": N_e not bracketed");
+    if (d == 0.0)
+      return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) + ": Fermi-level search did not finish");
+    if (d == 3.0)
+      return fail(p, SQ_E_NOCONV, "cell " + std::to_string(ci) +
+                                      ": Fermi-level search reached its update cap without meeting |N - N_e| <= 1e-13 N_e");
+  }
   long long off = 0;
   for (int ci : S->cells) {
     const CellHost& c = p->cells[ci];
@@ -799,10 +1115,10 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
         st = check_hip(p, hipMemcpyAsync(mu + i, &v, sizeof(double), hipMemcpyHostToDevice, s), "mu");
       else
         mu[i] = v;
+      if (st != SQ_OK) return st;
     }
   }
-  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(s), "density");
-  if (st == SQ_OK) st = verify_cells(p, "end of density");
+  if (rho || (mu && p->opt.outputs_on_device)) st = check_hip(p, hipStreamSynchronize(s), "density");
   if (st == SQ_OK)
     for (int ci : S->cells) {
       p->density_done[ci] = 1;
@@ -819,9 +1135,9 @@ sq_status sq_energy(sq_plan p, int cell, double* e_band) {
   for (int ci : S->cells)
     if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_energy before sq_density");
   hipStream_t s = p->stream;
-  phase_begin(p, PH_REDUCE);
+  phase_begin(p, PH_REDUCE, s);
   st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 1, 1, s), "reduce");
-  phase_end(p, PH_REDUCE);
+  phase_end(p, PH_REDUCE, s);
   std::vector<double> sums;
   if (st == SQ_OK) st = read_sums(p, sums);
   phase_collect(p);
@@ -870,12 +1186,12 @@ sq_status sq_pressure(sq_plan p, int cell, double* p_direct, double* p_trace) {
   // band energy and local-potential energy columns (the stress columns are
   // reduced by the stress pass)
   hipStream_t s = p->stream;
-  phase_begin(p, PH_REDUCE);
+  phase_begin(p, PH_REDUCE, s);
   if (st == SQ_OK)
     st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 1, 1, s), "reduce");
   if (st == SQ_OK)
     st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 21, 1, s), "reduce");
-  phase_end(p, PH_REDUCE);
+  phase_end(p, PH_REDUCE, s);
   if (st == SQ_OK) st = read_sums(p, sums);
   phase_collect(p);
   if (st != SQ_OK) return st;
@@ -900,9 +1216,9 @@ sq_status sq_xc(sq_plan p, int cell, double* e_xc, double* sigma_xc) {
   for (int ci : S->cells)
     if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_xc before sq_density");
   hipStream_t s = p->stream;
-  phase_begin(p, PH_REDUCE);
+  phase_begin(p, PH_REDUCE, s);
   st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 22, 2, s), "reduce");
-  phase_end(p, PH_REDUCE);
+  phase_end(p, PH_REDUCE, s);
   std::vector<double> sums;
   if (st == SQ_OK) st = read_sums(p, sums);
   phase_collect(p);

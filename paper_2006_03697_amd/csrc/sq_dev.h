@@ -12,12 +12,14 @@
 #define SQ_REC 24         // per-node record: rho, e, K[9], N[9], e_nl, dV V rho, xc energy, xc stress
 #define SQ_TILE 2         // nodes per tile edge for the image lists
 #define SQ_GRAM_MAX 1024  // projector pairs (I <= J) with overlapping supports in one cube
+#define SQ_CENSUS 8       // census ints per cell
 
 // error bits raised by kernels
 #define SQ_ERR_SLOTS 1u
 #define SQ_ERR_IMAGES 2u
 #define SQ_ERR_BOUNDS 4u
 #define SQ_ERR_NEAR 8u
+#define SQ_ERR_RANGE 16u   // a projection left the range of the fixed-point sums
 
 struct SpecDev {
   double v_amp, v_sig, v_rc, p_sig, p_rc, gamma;
@@ -31,7 +33,7 @@ struct CellDev {
   int nimg;           // atom images of the cell (all that reach any cube)
   int ntile[3];       // tiles per axis (SQ_TILE nodes per edge)
   int nsp;
-  int pad0;
+  int mq;             // Gauss-Chebyshev points of the coefficient integrals (0: per-node rule)
   int mu_mode;
   int pad1;
   long long Nd, node_base;
@@ -77,7 +79,7 @@ struct PlanDev {
 #define MU_HI 1
 #define MU_MID 2     // trial Fermi level of the next evaluation
 #define MU_VAL 3     // result
-#define MU_DONE 4    // 0 running, 1 done, 2 not bracketed
+#define MU_DONE 4    // 0 running, 1 done, 2 not bracketed, 3 update cap reached
 #define MU_IT 5
 #define MU_PHASE 6
 #define MU_N 7       // last electron count
@@ -86,17 +88,30 @@ struct PlanDev {
 #define MU_SIDE 10   // end point replaced last: -1 lo, +1 hi
 #define MU_WID 11    // bracket width at the last progress check
 
+// One launch of a recurrence kernel over a group of nodes of equal cube
+// width: the slot capacity needed per column (kc: the variant with the
+// smallest capacity >= kc runs), the single-sweep form (fused: the node's
+// Gram matrix is stored) and the launch form (counter != NULL: a persistent
+// grid of `grid` workgroups, or as many as the device holds at once when
+// grid <= 0, takes nodes from an atomic work counter, which the launcher
+// clears first; else one workgroup per node).
+struct RecLaunch {
+  int nc, kc;
+  bool fused;
+  unsigned* counter;
+  int grid;
+};
+
 extern "C++" {
 // launchers (sq_recur.hip per cube width, sq_misc.hip)
 hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s);
-// fused: the node's Gram matrix fits (one sweep per step); else two sweeps
-hipError_t sq_launch_lanczos(int nc, int kc, bool fused, const PlanDev& P, const long long* items,
+hipError_t sq_launch_lanczos(const RecLaunch& R, const PlanDev& P, const long long* items,
                              const int* item_cell, long long nitems, hipStream_t s);
-hipError_t sq_launch_gram(int nc, int kc, const PlanDev& P, const long long* items,
+hipError_t sq_launch_gram(int nc, const PlanDev& P, const long long* items,
                           const int* item_cell, long long nitems, hipStream_t s);
 hipError_t sq_launch_bounds(const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, hipStream_t s);
-hipError_t sq_launch_moments(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+hipError_t sq_launch_moments(const RecLaunch& R, bool fp64, const PlanDev& P,
                              const long long* items, const int* item_cell, long long nitems,
                              hipStream_t s);
 hipError_t sq_launch_mu_init(const PlanDev& P, const int* cells, int ncells, const int* fixed_mode,
@@ -106,13 +121,17 @@ hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int
 hipError_t sq_launch_mu_step(const PlanDev& P, const int* cells, int ncells, hipStream_t s);
 hipError_t sq_launch_coeffs(const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, hipStream_t s);
-hipError_t sq_launch_stress(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+hipError_t sq_launch_stress(const RecLaunch& R, bool fp64, const PlanDev& P,
                             const long long* items, const int* item_cell, long long nitems,
                             hipStream_t s);
 hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, int* stats, long long* pairs, hipStream_t s);
-int sq_kc_limit(bool fp64, int nc);
+hipError_t sq_launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
+// slot capacity of the variant that serves a need of kc slots per column
+// (0: none)
+int sq_kc_variant(bool fused, int kc);
 int sq_img_limit(int nc);
+int sq_gram_limit(int nc);
 hipError_t sq_launch_reduce(const PlanDev& P, const int* cells, int ncells, int col0, int ncol,
                             hipStream_t s);
 bool sq_nc_supported(int nc);

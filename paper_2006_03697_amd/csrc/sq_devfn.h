@@ -68,6 +68,55 @@ __device__ __forceinline__ double warp_sum(double v) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Deterministic sums of FP64 terms: each term x is split into two integers,
+// x = hi 2^-30 + lo 2^-80 (hi = x 2^30 rounded to an integer, lo = the
+// remainder 2^50 rounded), and the integers are added with 64-bit integer
+// atomics.  Integer addition is associative, so the sum does not depend on
+// the order in which the terms arrive: a result is the same bit for bit on
+// every run and in every batch.  Each term is rounded to 2^-81 (absolute);
+// |x| < 2^20 is required (checked by the caller), and up to 2^13 terms of
+// that size fit the integer range.  The rounding to integers uses the
+// 1.5 2^52 shift: for |y| < 2^51, y + 1.5 2^52 carries y rounded to the
+// nearest integer in its low mantissa bits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long fx_round_bits(double y, double& yr) {
+#pragma clang fp contract(off)
+  const double M = 6755399441055744.0;   // 1.5 * 2^52
+  const double t = y + M;
+  yr = t - M;
+  return (long long)(__double_as_longlong(t) - __double_as_longlong(M));
+}
+
+__device__ __forceinline__ void fx_split(double x, long long& hi, long long& lo) {
+#pragma clang fp contract(off)
+  const double xs = x * 0x1p30;
+  double hr;
+  hi = fx_round_bits(xs, hr);
+  const double rem = xs - hr;              // exact, |rem| <= 1/2
+  double lr;
+  lo = fx_round_bits(rem * 0x1p50, lr);
+}
+
+__device__ __forceinline__ double fx_join(long long hi, long long lo) {
+  return (double)hi * 0x1p-30 + (double)lo * 0x1p-80;
+}
+
+// Adds x to the two-word accumulator p[0..1] (LDS), without branches; a
+// term with |x| >= 2^20 (or not a number) is replaced by zero and sets bad.
+__device__ __forceinline__ void fx_add(unsigned long long* p, double x, bool& bad) {
+  const bool ok = fabs(x) < 0x1p20;
+  bad = bad || !ok;
+  long long hi, lo;
+  fx_split(ok ? x : 0.0, hi, lo);
+  atomicAdd(&p[0], (unsigned long long)hi);
+  atomicAdd(&p[1], (unsigned long long)lo);
+}
+
+__device__ __forceinline__ double fx_load(const unsigned long long* p) {
+  return fx_join((long long)p[0], (long long)p[1]);
+}
+
 __device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
   double t = ceil(8.0 * zeta / kT);
   double tgt = fmax((double)(4 * (npl + 2)), t);
@@ -87,23 +136,36 @@ __device__ __forceinline__ int quad_points(double zeta, double kT, int npl) {
 #define SQ_NC_LIST(X) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25)
 
 #define SQ_DECL_NC(N)                                                                          \
-  hipError_t sq_launch_lanczos_##N(int kc, bool fused, const PlanDev& P, const long long* items, \
+  hipError_t sq_launch_lanczos_##N(const RecLaunch& R, const PlanDev& P, const long long* items, \
                                    const int* ic, long long n, hipStream_t s);                \
-  hipError_t sq_launch_moments_##N(bool fp64, int kc, bool fused, const PlanDev& P,            \
+  hipError_t sq_launch_moments_##N(const RecLaunch& R, bool fp64, const PlanDev& P,            \
                                    const long long* items, const int* ic, long long n,        \
                                    hipStream_t s);                                            \
-  hipError_t sq_launch_stress_##N(bool fp64, int kc, bool fused, const PlanDev& P,             \
+  hipError_t sq_launch_stress_##N(const RecLaunch& R, bool fp64, const PlanDev& P,             \
                                   const long long* items, const int* ic, long long n,         \
                                   hipStream_t s);                                             \
-  hipError_t sq_launch_gram_##N(int kc, const PlanDev& P, const long long* items, const int* ic, \
+  hipError_t sq_launch_gram_##N(const PlanDev& P, const long long* items, const int* ic,       \
                                 long long n, hipStream_t s);                                  \
   hipError_t sq_launch_census_##N(const PlanDev& P, const long long* items, const int* ic,     \
                                   long long n, int* stats, long long* pairs, hipStream_t s);
 SQ_NC_LIST(SQ_DECL_NC)
 
-// Largest slot capacity per precision and width (0: unsupported).
-__host__ __device__ constexpr int sq_kc_max(bool, int) { return 48; }
+__host__ __device__ constexpr int sq_threads(int nc) { return ((nc * nc + 63) / 64) * 64; }
+
+// Slot capacities compiled per single-sweep form: the smallest that holds
+// kc (16: plane-0 weights kept in registers; 48: recomputed); two-sweep
+// nodes: 48.  0: none.
+__host__ __device__ constexpr int sq_kc_pick(bool fused, int kc) {
+  return !fused ? (kc <= 48 ? 48 : 0) : (kc <= 16 ? 16 : (kc <= 48 ? 48 : 0));
+}
 
 // Largest number of atom images one cube may see (the image index shares a
-// 32-bit slot word with the chord bits of the NC planes).
+// 32-bit slot word with the chord bits of the planes of one thread).
 __host__ __device__ constexpr int sq_img_max(int nc) { return (1 << (32 - nc)) < 160 ? (1 << (32 - nc)) : 160; }
+
+// Gram entries a node may store for the single-sweep form: at most four
+// per thread of the workgroup (each thread adds up to four Gram terms per
+// step), and at most SQ_GRAM_MAX.
+__host__ __device__ constexpr int sq_gram_cap(int nc) {
+  return 4 * sq_threads(nc) < SQ_GRAM_MAX ? 4 * sq_threads(nc) : SQ_GRAM_MAX;
+}

@@ -119,9 +119,10 @@ struct Window {
   double muh, sigh;
 };
 
-__device__ __forceinline__ Window fermi_window(double mu, double chi, double zeta, double kT, int npl) {
+__device__ __forceinline__ Window fermi_window(double mu, double chi, double zeta, const CellDev& C) {
   Window W;
-  W.M = quad_points(zeta, kT, npl);
+  const double kT = C.kT;
+  W.M = C.mq > 0 ? C.mq : quad_points(zeta, kT, C.npl);
   W.muh = (mu - chi) / zeta;
   W.sigh = kT / zeta;
   const double xb = W.muh + 40.0 * W.sigh;   // above: occupation 0
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(256) k_mu_eval(PlanDev P, const long long* ite
   for (int j = lane; j <= npl; j += 64) smom[wv][j] = mom[j];
   wave_sync();
   const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
-  const Window W = fermi_window(mus[MU_MID], chi, zeta, C.kT, npl);
+  const Window W = fermi_window(mus[MU_MID], chi, zeta, C);
   double acc = 0.0, dacc = 0.0;
   // occupied tail: sum'_j rho^j S_j(ka + 1)
   for (int j = lane; j <= npl; j += 64) {
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(256) k_coeffs(PlanDev P, const long long* item
   const int npl = C.npl;
   const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
   const double mu = P.mus[SQ_MU_STRIDE * ci + MU_VAL];
-  const Window W = fermi_window(mu, chi, zeta, C.kT, npl);
+  const Window W = fermi_window(mu, chi, zeta, C);
   const double* mom = P.mom + g * P.mstride;
   // per lane: coefficients j = lane + 64 r
   double cacc[5] = {0, 0, 0, 0, 0};
@@ -405,9 +406,12 @@ __global__ void __launch_bounds__(256) k_mu_step(PlanDev P, const int* cells) {
       m[MU_SIDE] = -1.0;
     }
     m[MU_IT] += 1.0;
-    if (m[MU_IT] >= 200.0 || !(hi - lo > 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)))) {
+    // a bracket collapsed to rounding level is a root to machine precision;
+    // the update cap without that is a search that did not converge
+    const bool collapsed = !(hi - lo > 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
+    if (collapsed || m[MU_IT] >= 200.0) {
       m[MU_VAL] = mid;
-      m[MU_DONE] = 1.0;
+      m[MU_DONE] = collapsed ? 1.0 : 3.0;
       m[MU_LO] = lo;
       m[MU_HI] = hi;
       return;
@@ -447,6 +451,13 @@ __global__ void __launch_bounds__(256) k_reduce(PlanDev P, const int* cells, int
   }
 }
 
+// p[0 .. n) = v.  Clears counters and flags with an ordinary kernel (also
+// inside a captured graph).
+__global__ void __launch_bounds__(256) k_fill_u32(unsigned* p, unsigned v, long long n) {
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // Local potential on the periodic grid: sum over atom images within v_rcut.
 __global__ void __launch_bounds__(256) k_vloc(const CellDev* cell, double* out) {
   const CellDev& C = *cell;
@@ -476,49 +487,57 @@ bool sq_nc_supported(int nc) {
   return false;
 }
 
-int sq_kc_limit(bool fp64, int nc) { return sq_kc_max(fp64, nc); }
+int sq_kc_variant(bool fused, int kc) { return sq_kc_pick(fused, kc); }
 
 int sq_img_limit(int nc) { return sq_img_max(nc); }
 
-hipError_t sq_launch_lanczos(int nc, int kc, bool fused, const PlanDev& P, const long long* items,
+int sq_gram_limit(int nc) { return sq_gram_cap(nc); }
+
+hipError_t sq_launch_lanczos(const RecLaunch& R, const PlanDev& P, const long long* items,
                              const int* item_cell, long long nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
 #define SQ_CASE(N) \
-  if (nc == N) return sq_launch_lanczos_##N(kc, fused, P, items, item_cell, nitems, s);
+  if (R.nc == N) return sq_launch_lanczos_##N(R, P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t sq_launch_gram(int nc, int kc, const PlanDev& P, const long long* items,
+hipError_t sq_launch_gram(int nc, const PlanDev& P, const long long* items,
                           const int* item_cell, long long nitems, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-#define SQ_CASE(N) if (nc == N) return sq_launch_gram_##N(kc, P, items, item_cell, nitems, s);
+#define SQ_CASE(N) if (nc == N) return sq_launch_gram_##N(P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t sq_launch_moments(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+hipError_t sq_launch_moments(const RecLaunch& R, bool fp64, const PlanDev& P,
                              const long long* items, const int* item_cell, long long nitems,
                              hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
 #define SQ_CASE(N) \
-  if (nc == N) return sq_launch_moments_##N(fp64, kc, fused, P, items, item_cell, nitems, s);
+  if (R.nc == N) return sq_launch_moments_##N(R, fp64, P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t sq_launch_stress(int nc, int kc, bool fp64, bool fused, const PlanDev& P,
+hipError_t sq_launch_stress(const RecLaunch& R, bool fp64, const PlanDev& P,
                             const long long* items, const int* item_cell, long long nitems,
                             hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
 #define SQ_CASE(N) \
-  if (nc == N) return sq_launch_stress_##N(fp64, kc, fused, P, items, item_cell, nitems, s);
+  if (R.nc == N) return sq_launch_stress_##N(R, fp64, P, items, item_cell, nitems, s);
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t sq_launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
 }
 
 hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,

@@ -5,17 +5,18 @@
 // (SQ_ONE_NC).
 //
 // One workgroup owns one node q and its cube (region of influence) of
-// NC^3 finite-difference nodes.  Thread (cx, cy) owns the z-column of the
-// cube at (cx, cy): the current Chebyshev vector, the previous one and the
+// NC^3 finite-difference nodes.  Thread (cx, cy) owns the z-column (cx, cy)
+// of the cube: the current Chebyshev vector, the previous one and the
 // diagonal of H_q on that column live in its registers; the current vector
-// is mirrored in LDS so that x/y neighbours of the 12th-order stencil are
-// LDS reads and z neighbours are register reads.  Atom-image projectors are
+// is mirrored in LDS so that x/y neighbours of the 12th-order stencil are LDS
+// reads and z neighbours register reads.  Atom-image projectors are
 // separable Gaussians cut off at a sphere: per (column, image) the chord of
 // the sphere on the column as a bit mask and the projector value at the
 // column's first plane (registers, computed once per node); along the column
-// the Gaussian factor follows from a two-multiply recurrence.  One sweep per
-// operator application both adds the projector terms and takes the new
-// projections (completed by the stored Gram matrix of the node's projectors).
+// the Gaussian factor follows from a two-multiply recurrence.  One sweep per operator application both adds
+// the projector terms and takes the new projections (completed by the stored
+// Gram matrix of the node's projectors).  Projections are summed exactly in
+// two-word integers, so every result is reproducible bit for bit.
 #include "sq_devfn.h"
 
 #ifndef SQ_ONE_NC
@@ -26,12 +27,9 @@ namespace {
 // ---------------------------------------------------------------------------
 // Cube layout in LDS and the thread <-> z-column map
 //
-// Thread (cx, cy) owns the z-column (cx, cy) of the cube: the current and
-// previous Chebyshev vectors and the diagonal live in its registers, and the
-// current vector is mirrored in LDS for the x and y neighbours of the
-// stencil.  Padded layout: rows of RS >= NC + 6 elements (the tail zero) and
-// planes of NC + 6 rows (the last 6 zero), after 6 zero rows and 6 zeros, so
-// every neighbour outside the cube reads a zero and needs no predicate.
+// Padded layout: rows of RS >= NC + 6 elements (the tail zero) and planes of
+// NC + 6 rows (the last 6 zero), after 6 zero rows and 6 zeros, so every x/y
+// neighbour outside the cube reads a zero and needs no predicate; the zero
 //
 // LDS has 32 banks of 4 bytes: a 32-bit access by 32 lanes, or a 64-bit
 // access by 16 lanes, is conflict-free when the element addresses are
@@ -54,8 +52,6 @@ constexpr int sq_residue_max(int nc, int rs) {
   return mx;
 }
 
-constexpr int sq_threads(int nc) { return ((nc * nc + 63) / 64) * 64; }
-
 constexpr int sq_pick_rs(int nc) {
   for (int rs = nc + SQ_FDM; rs <= nc + SQ_FDM + 16; ++rs)
     if (sq_residue_max(nc, rs) * 32 <= sq_threads(nc)) return rs;
@@ -64,8 +60,7 @@ constexpr int sq_pick_rs(int nc) {
 
 template <int NC, bool PAD>
 struct Lay {
-  static constexpr int NT = sq_threads(NC);
-  static constexpr int NW = NT / 64;
+  static constexpr int NTC = sq_threads(NC);   // threads (one per column)
   static constexpr int MH = NC / 2;
   static constexpr int RS = PAD ? sq_pick_rs(NC) : NC;              // row stride
   static constexpr int PL = PAD ? (NC + SQ_FDM) * RS : NC * NC;     // plane stride
@@ -74,13 +69,13 @@ struct Lay {
   static_assert(!PAD || RS > 0, "no conflict-free row stride");
   __device__ static constexpr int at(int x, int y, int z) { return X0 + z * PL + y * RS + x; }
 
-  // Column of thread tid (see above); inactive threads own no column.
-  __device__ static void column(int tid, int& cx, int& cy, bool& active) {
+  // Column of local thread t (see above); inactive threads own no column.
+  __device__ static void column(int t, int& cx, int& cy, bool& active) {
     cx = 0;
     cy = 0;
     active = false;
     if constexpr (PAD) {
-      const int r = tid & 31, g = tid >> 5;
+      const int r = t & 31, g = t >> 5;
       int seen = 0;
       for (int y = 0; y < NC; ++y) {
         const int x = (r - y * RS) & 31;   // the one column of row y with residue r
@@ -94,9 +89,9 @@ struct Lay {
         }
       }
     } else {
-      active = tid < NC * NC;
-      cx = tid % NC;
-      cy = tid / NC;
+      active = t < NC * NC;
+      cx = t % NC;
+      cy = t / NC;
     }
   }
 };
@@ -104,32 +99,44 @@ struct Lay {
 // A kernel variant: working precision T, cube width NC, KC projector slots
 // per z-column, and whether each slot's weight on plane 0 is kept in a
 // register (AREG) or recomputed at every use.  The padded LDS layout is used
-// when the whole working set fits the 160 KiB of LDS.
+// when the working set fits the 160 KiB of LDS.
 template <typename T_, int NC_, int KC_, bool AREG_>
 struct Var {
   using T = T_;
   static constexpr int NC = NC_;
   static constexpr int KC = KC_;
   static constexpr bool AREG = AREG_;
-  // slot word: chord bits 31 .. 32 - NC, image index below
-  static constexpr int IBITS = 32 - NC_;
-  static constexpr int NIMG = (1 << IBITS) < 160 ? (1 << IBITS) : 160;
+  static constexpr int ZH = NC_;   // planes per thread (the whole column)
+  static constexpr int NTC = sq_threads(NC_);
+  static constexpr int NT = NTC;
+  static constexpr int NW = NT / 64;
+  // slot word: chord bits 31 .. 32 - ZH, image index below
+  static constexpr int IBITS = 32 - ZH;
+  static constexpr int NIMG = sq_img_max(NC_);
   static constexpr int NEAR = SQ_NEAR_MAX;
-  static constexpr size_t OTHER = 8 * (size_t)NIMG * 11 + (size_t)NEAR * 11 * 8 + NEAR * 4 + 1024 +
-                                  12 * (size_t)SQ_GRAM_MAX;
-  // scratch of the Gram build (FP64 Lanczos pass only), in the cube buffer:
-  // pair bitmap [NIMG][NWD], row starts [NIMG + 1], slot words [KC][NT]
+  static constexpr int GCAP = sq_gram_cap(NC_);
+  static constexpr int GPT = (GCAP + NT - 1) / NT;   // Gram entries per thread (registers)
+  static_assert(NIMG <= (1 << IBITS) && NIMG <= 65536, "image index width");
+  static_assert(NT <= 1024, "workgroup size");
+  static constexpr size_t OTHER = 8 * (size_t)NIMG * 9 + 8 * 2 * (size_t)NIMG +
+                                  16 * (size_t)NIMG + 16 * (size_t)NEAR * 10 + (size_t)NEAR * 12 +
+                                  2 * 2 * 16 * 8 + 8 * 9 * (2 * SQ_FDM + 1) + 256;
+  // scratch of the Gram build in the cube buffer: pair bitmap [NIMG][NWD],
+  // row starts [NIMG + 1], slot words [KC][NT], two-word sums [GCAP][2]
   static constexpr int NWD = (NIMG + 31) / 32;
-  static constexpr size_t GSCR = 4 * ((size_t)NIMG * NWD + NIMG + 1 + (size_t)KC * sq_threads(NC_));
+  static constexpr size_t GSCR = 4 * ((size_t)NIMG * NWD + NIMG + 1 + (size_t)KC * NT) + 8 +
+                                 16 * (size_t)GCAP;
 #ifdef SQ_NO_PAD
   static constexpr bool PAD = false;
 #else
   static constexpr bool PAD = sizeof(T_) * (size_t)Lay<NC_, true>::SIZE + OTHER <= 163840;
 #endif
   using L = Lay<NC_, PAD>;
-  // elements of the cube buffer: the padded or plain cube, or the Gram scratch
-  static constexpr size_t TLN = (sizeof(T_) == 8 && (GSCR + 7) / 8 > (size_t)L::SIZE) ? (GSCR + 7) / 8
-                                                                                   : (size_t)L::SIZE;
+  static constexpr int MH = NC_ / 2;
+  // elements of the cube buffer: the cube, or the Gram scratch
+  static constexpr size_t TLN = (GSCR + sizeof(T_) - 1) / sizeof(T_) > (size_t)L::SIZE
+                                    ? (GSCR + sizeof(T_) - 1) / sizeof(T_)
+                                    : (size_t)L::SIZE;
 };
 
 template <class Vr>
@@ -137,23 +144,21 @@ struct Smem {
   using T = typename Vr::T;
   static constexpr int NI = Vr::NIMG;
   T tl[Vr::TLN];
-  double ix[NI], iy[NI], iz[NI];      // image positions (unwrapped)
+  double ix[NI], iy[NI], iz[NI];      // image positions (unwrapped), sorted by z
   double rp2[NI], i2s[NI], gdv[NI];   // r_p^2, 1 / (2 sigma_p^2), gamma dV
   // z factor of each image on the cube planes: e(z) = exp(-u_z^2 i2s) with
   // u_z = u_0 + z h, generated as e(z + 1) = e(z) rr(z), rr(z + 1) = rr(z) cq
   double e0[NI], r0[NI], cq[NI];
-  double pacc[2][NI];                 // projections, double-buffered over steps
-  // Gram matrix <chi_I, chi_J> over the cube for I <= J with overlapping
-  // supports: value and I | J << 16, ngram entries in (I, J) order
-  double gval[SQ_GRAM_MAX];
-  unsigned gidx[SQ_GRAM_MAX];
-  int ngram;
+  double pf[2][NI];                   // projections <chi_I, v>, double-buffered over steps
+  unsigned long long pint[NI][2];     // projection sums being formed (two-word integers)
+  unsigned long long nsum[Vr::NEAR][10][2];   // stress pass: sums over near images' supports
+  double kl[3][3][2 * SQ_FDM + 1];    // stress pass: G_b = grad_b d on the line through the node along a
   double red[2][2 * 16];              // block sums, double-buffered over steps
   double near_chi[Vr::NEAR];
-  double nsum[Vr::NEAR][10];
   int near_img[Vr::NEAR];
   int wcnt[16];
-  int nimg, nnear;
+  int nimg, nnear, ngram;
+  unsigned item;
 };
 
 // Per-thread node context (registers).
@@ -165,11 +170,17 @@ struct Ctx {
   long long q0, q1, q2;
   int nslot;    // slots of this column
   int nsw;      // largest slot count in the wave (wave-uniform)
+  int bown;     // LDS element offset of the column's plane 0
   // slot s: bit 31 - z set for the planes z of the chord of the image's
   // spherical support on this column; the image index in the low bits
   unsigned sid[Vr::KC];
   double a0[Vr::AREG ? Vr::KC : 1];   // projector value of slot s at (cx, cy, plane 0)
-  T vd[Vr::NC];                       // diagonal of (H_q - shift) without the stencil centre
+  T vd[Vr::ZH];                       // diagonal of (H_q - shift) without the stencil centre
+  // the node's stored Gram entries (global memory, read at every step)
+  const double* gvp;
+  const unsigned* gip;
+  int ngram;
+  bool bad;     // a fixed-point term was out of range
 };
 
 template <class Vr>
@@ -178,7 +189,7 @@ __device__ __forceinline__ double slot_start(const Smem<Vr>& S, const Ctx<Vr>& X
   if constexpr (Vr::AREG) {
     return X.a0[s];
   } else {
-    constexpr int m = Vr::NC / 2;
+    constexpr int m = Vr::MH;
     const double dx = node_coord(X.q0 + X.cx - m, C.h, S.ix[i]);
     const double dy = node_coord(X.q1 + X.cy - m, C.h, S.iy[i]);
     return exp(-sq_sum2(dx, dy) * S.i2s[i]) * S.e0[i];
@@ -247,16 +258,19 @@ __device__ __forceinline__ int wave_max(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Node prologue: image list of the cube, z-factor constants, per-column
-// chords and projector weights, diagonal.  shift is subtracted from the
-// diagonal.
+// Node prologue: image list of the cube (sorted by z, ties in gather order),
+// z-factor constants, per-column chords and projector weights, diagonal,
+// projection buffers.  shift is subtracted from the diagonal.
 template <class Vr>
 __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, double shift,
                                               Smem<Vr>& S, Ctx<Vr>& X, unsigned* err) {
   using T = typename Vr::T;
   using L = typename Vr::L;
   constexpr int NC = Vr::NC;
-  constexpr int m = L::MH;
+  constexpr int ZH = Vr::ZH;
+  constexpr int NT = Vr::NT;
+  constexpr int NI = Vr::NIMG;
+  constexpr int m = Vr::MH;
   const int tid = threadIdx.x;
   L::column(tid, X.cx, X.cy, X.active);
   X.col = X.cx + NC * X.cy;
@@ -275,17 +289,46 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     S.i2s[pos] = 1.0 / (2.0 * s.p_sig * s.p_sig);
     S.gdv[pos] = s.gamma * C.dV;
   };
-  const int found = gather_images<L::NT, L::NW, Vr::NIMG>(C, X.q0, X.q1, X.q2, m, &S.nimg,
-                                                           S.wcnt, store, err);
-  const int nimg = found < Vr::NIMG ? found : Vr::NIMG;
+  const int found = gather_images<NT, Vr::NW, NI>(C, X.q0, X.q1, X.q2, m, &S.nimg, S.wcnt, store, err);
+  const int nimg = found < NI ? found : NI;
   if (tid == 0) S.nimg = nimg;
 
-  // ---- z-factor constants of every image; projection accumulators ----
-  for (int i = tid; i < Vr::NIMG; i += L::NT) {
+  // ---- sort by z (rank by (z, gather position)); scratch in the cube buffer ----
+  {
+    double* scr = reinterpret_cast<double*>(S.tl);   // [6][NI]
+    static_assert(sizeof(S.tl) >= 6 * sizeof(double) * NI, "sort scratch");
+    for (int t = tid; t < nimg; t += NT) {
+      const double zt = S.iz[t];
+      int r = 0;
+      for (int j = 0; j < nimg; ++j) {
+        const double zj = S.iz[j];
+        r += (zj < zt || (zj == zt && j < t)) ? 1 : 0;
+      }
+      scr[r] = S.ix[t];
+      scr[NI + r] = S.iy[t];
+      scr[2 * NI + r] = zt;
+      scr[3 * NI + r] = S.rp2[t];
+      scr[4 * NI + r] = S.i2s[t];
+      scr[5 * NI + r] = S.gdv[t];
+    }
+    __syncthreads();
+    for (int t = tid; t < nimg; t += NT) {
+      S.ix[t] = scr[t];
+      S.iy[t] = scr[NI + t];
+      S.iz[t] = scr[2 * NI + t];
+      S.rp2[t] = scr[3 * NI + t];
+      S.i2s[t] = scr[4 * NI + t];
+      S.gdv[t] = scr[5 * NI + t];
+    }
+    __syncthreads();
+  }
+
+  // ---- z-factor constants of every image; projections ----
+  for (int i = tid; i < NI; i += NT) {
     double e0 = 0.0, r0 = 0.0, cq = 0.0;
     if (i < nimg) {
-      const double u0 = node_coord(X.q2 - m, h, S.iz[i]);
       const double is = S.i2s[i];
+      const double u0 = node_coord(X.q2 - m, h, S.iz[i]);
       e0 = exp(-(u0 * u0) * is);
       r0 = exp(-(2.0 * u0 * h + h * h) * is);
       cq = exp(-2.0 * h * h * is);
@@ -293,10 +336,12 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     S.e0[i] = e0;
     S.r0[i] = r0;
     S.cq[i] = cq;
-    S.pacc[0][i] = 0.0;
-    S.pacc[1][i] = 0.0;
+    S.pf[0][i] = 0.0;
+    S.pf[1][i] = 0.0;
+    S.pint[i][0] = 0ull;
+    S.pint[i][1] = 0ull;
   }
-  for (int i = tid; i < L::SIZE; i += L::NT) S.tl[i] = (T)0;
+  for (int i = tid; i < (int)Vr::TLN; i += NT) S.tl[i] = (T)0;
   if (tid == 0) S.nnear = 0;
   __syncthreads();
 
@@ -351,6 +396,11 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     }
     X.vd[z] = (T)(v + cdiag - shift);
   }
+  X.bown = L::at(X.cx, X.cy, 0);
+  X.gvp = nullptr;
+  X.gip = nullptr;
+  X.ngram = 0;
+  X.bad = false;
 }
 
 // Weight of a slot on one plane in the working precision: a on the chord,
@@ -372,12 +422,13 @@ __device__ __forceinline__ double chord_weight<double>(bool on, double a) {
   return __longlong_as_double((long long)((hi << 32) | (b & 0xffffffffull)));
 }
 
-// Projector weights of one slot along the column: w(z) = a e(z)/e(0) on the
-// planes of the chord, zero elsewhere.  f(z, w) is called for every plane.
-template <int NC, class F>
+// Projector weights of one slot along the column: w(z) = a e(z)/e(0)
+// on the planes of the chord, zero elsewhere.  f(z, on, w) is called for
+// every plane.
+template <int ZH, class F>
 __device__ __forceinline__ void slot_sweep(unsigned mk, double a, double rr, double cq, F f) {
 #pragma unroll
-  for (int z = 0; z < NC; ++z) {
+  for (int z = 0; z < ZH; ++z) {
     unsigned nm;
     const bool on = __builtin_add_overflow(mk, mk, &nm);   // bit 31 - z
     mk = nm;
@@ -388,13 +439,12 @@ __device__ __forceinline__ void slot_sweep(unsigned mk, double a, double rr, dou
   }
 }
 
-// Projections <chi_I, v> of the vector v held in registers into S.pacc[buf]
-// (the caller places a barrier before they are read).
+// Projections <chi_I, v> of the vector v held in registers, added to
+// S.pint (the caller places a barrier before they are read).
 template <class Vr>
-__device__ __forceinline__ void project(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C,
-                                        const typename Vr::T (&v)[Vr::NC], int buf) {
+__device__ __forceinline__ void project(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
+                                        const typename Vr::T (&v)[Vr::ZH]) {
   using T = typename Vr::T;
-  constexpr int NC = Vr::NC;
   constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
 #pragma unroll
   for (int s = 0; s < Vr::KC; ++s) {
@@ -402,10 +452,26 @@ __device__ __forceinline__ void project(Smem<Vr>& S, const Ctx<Vr>& X, const Cel
       const unsigned mk = X.sid[s];
       const int i = (int)(mk & IMASK);
       T part = (T)0;
-      slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
-                     [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
-      if (s < X.nslot) atomicAdd(&S.pacc[buf][i], (double)part);
+      slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                         [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
+      // a slot past the thread's count has sid 0 and weight zero: it adds 0 to image 0
+      fx_add(S.pint[i], (double)part, X.bad);
     }
+  }
+}
+
+// After the barrier that ends a step: the new projections
+// pf[par ^ 1] = (sum - alpha pf[par]) * ib from the integer sums, which are
+// cleared for the next step (the caller places a barrier before either is
+// used again).
+template <class Vr>
+__device__ __forceinline__ void finish_proj(Smem<Vr>& S, int par, double alpha = 0.0, double ib = 1.0) {
+  for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::NT) {
+    double v = fx_load(S.pint[i]);
+    if (alpha != 0.0) v -= alpha * S.pf[par][i];
+    S.pf[par ^ 1][i] = v * ib;
+    S.pint[i][0] = 0ull;
+    S.pint[i][1] = 0ull;
   }
 }
 
@@ -415,25 +481,25 @@ __device__ __forceinline__ void project(Smem<Vr>& S, const Ctx<Vr>& X, const Cel
 // io holds the previous vector on entry and the new one on exit (registers
 // only; the caller mirrors it).
 //
-// Projections: S.pacc[par] holds <chi_I, cur> on entry and S.pacc[par ^ 1]
-// is zero; on exit S.pacc[par ^ 1] holds <chi_I, io>.  FUSED: they come out
+// Projections: S.pf[par] holds <chi_I, cur> on entry and S.pint is zero; on
+// exit S.pint holds the integer sums of <chi_I, io>.  FUSED: they come out
 // of the same sweep that adds the projector terms c_I chi_I, c_I = sc gamma
-// dV <chi_I, cur>: every column visits its images in increasing index, and
-// the projection onto chi_I is taken before the column adds c_I chi_I, so the
-// sweep yields <chi_I, u> + sum_{J < I} c_J G_IJ (u the stencil part of io,
-// G the Gram matrix of the projectors over the cube); the missing
+// dV <chi_I, cur>: every thread visits its images in increasing index, and
+// the projection onto chi_I is taken before the thread adds c_I chi_I, so
+// the sweep yields <chi_I, u> + sum_{J < I} c_J G_IJ (u the stencil part of
+// io, G the Gram matrix of the projectors over the cube); the missing
 // sum_{J >= I} G_IJ c_J is added from the stored upper triangle.  Otherwise
 // (a cube whose Gram matrix exceeds its capacity) a second sweep projects
-// the finished io.  The caller clears S.pacc[par] before the next step.
-// Ends after one block barrier.
+// the finished io.  Ends after one block barrier; the caller then forms
+// S.pf[par ^ 1] with finish_proj.
 template <class Vr, bool FUSED>
 __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
-                                           const typename Vr::T (&cur)[Vr::NC],
-                                           typename Vr::T (&io)[Vr::NC], const typename Vr::T* ck,
+                                           const typename Vr::T (&cur)[Vr::ZH],
+                                           typename Vr::T (&io)[Vr::ZH], const typename Vr::T* ck,
                                            double sc, typename Vr::T pm, int par, double cw = 0.0) {
   using T = typename Vr::T;
   using L = typename Vr::L;
-  constexpr int NC = Vr::NC;
+  constexpr int ZH = Vr::ZH;
   constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
   const int nsw = X.nsw;
   // keep the per-slot data opaque so that nothing derived from it is hoisted
@@ -445,35 +511,45 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
     for (int s = 0; s < Vr::KC; ++s) opaque(X.a0[s]);
   }
   if constexpr (FUSED) {
-    // (1) the upper-triangle Gram terms of the new projections
-    const int ngram = S.ngram;
-    for (int e = threadIdx.x; e < ngram; e += L::NT) {
-      const unsigned ij = S.gidx[e];
-      const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
-      atomicAdd(&S.pacc[par ^ 1][i], S.gval[e] * (sc * S.gdv[j] * S.pacc[par][j]));
+    // (1) the upper-triangle Gram terms of the new projections (entries from
+    // global memory, cached: the same few kilobytes at every step); a
+    // thread past the count adds zero to image 0
+    const int ng = X.ngram;
+    if (ng > 0) {
+#pragma unroll
+      for (int e = 0; e < Vr::GPT; ++e) {
+        const int k = threadIdx.x + e * Vr::NT;
+        if (e * Vr::NT < ng) {   // uniform
+          const bool in = k < ng;
+          const int kk = in ? k : ng - 1;
+          const double gval = X.gvp[kk];
+          const unsigned ij = in ? X.gip[kk] : 0u;
+          const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
+          fx_add(S.pint[i], in ? gval * (sc * S.gdv[j] * S.pf[par][j]) : 0.0, X.bad);
+        }
+      }
     }
   }
-  // (2) stencil + diagonal on the own column (x/y neighbours from LDS)
+  // (2) stencil + diagonal on the own planes (x/y neighbours from LDS, z
+  // neighbours from registers or, across the plane split, from LDS)
   if (X.active) {
-    const int cx = X.cx, cy = X.cy;
-    const int base = L::at(cx, cy, 0);
     const T tsc = (T)sc;
 #pragma unroll
-    for (int z = 0; z < NC; ++z) {
+    for (int z = 0; z < ZH; ++z) {
       T acc = X.vd[z] * cur[z];
-      const T* pc = S.tl + base + z * L::PL;
+      const T* pc = S.tl + X.bown + z * L::PL;
 #pragma unroll
       for (int k = 1; k <= SQ_FDM; ++k) {
         T s = (T)0;
-        if (z + k < NC) s += cur[z + k];
+        if (z + k < ZH) s += cur[z + k];
         if (z - k >= 0) s += cur[z - k];
-        if constexpr (L::RS > NC) {
+        if constexpr (L::RS > Vr::NC) {
           s += (pc[k] + pc[-k]) + (pc[k * L::RS] + pc[-k * L::RS]);
         } else {
-          if (cx + k < NC) s += pc[k];
-          if (cx - k >= 0) s += pc[-k];
-          if (cy + k < NC) s += pc[k * L::RS];
-          if (cy - k >= 0) s += pc[-k * L::RS];
+          if (X.cx + k < Vr::NC) s += pc[k];
+          if (X.cx - k >= 0) s += pc[-k];
+          if (X.cy + k < Vr::NC) s += pc[k * L::RS];
+          if (X.cy - k >= 0) s += pc[-k * L::RS];
         }
         acc += ck[k] * s;
       }
@@ -481,24 +557,25 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
     }
     // optional cw w_q (the unit vector at the node): part of the vector the
     // projector terms are added to, and of its projections
-    if (X.cx == Vr::NC / 2 && X.cy == Vr::NC / 2) io[Vr::NC / 2] += (T)cw;
+    if (X.cx == Vr::MH && X.cy == Vr::MH) io[Vr::MH] += (T)cw;
   }
   if constexpr (FUSED) {
     // (3) one sweep per image: projection of io, then the projector term
+    // (a slot past the thread's count has sid 0: weight zero, image 0)
 #pragma unroll
     for (int s = 0; s < Vr::KC; ++s) {
       if (s < nsw) {
         const unsigned mk = X.sid[s];
         const int i = (int)(mk & IMASK);
-        const T coef = (T)(s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0);
+        const T coef = (T)(sc * S.gdv[i] * S.pf[par][i]);
         T part = (T)0;
-        slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+        slot_sweep<ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
                        [&](int z, bool on, double a) {
                          const T w = chord_weight<T>(on, a);
                          part += w * io[z];
                          io[z] += w * coef;
                        });
-        if (s < X.nslot) atomicAdd(&S.pacc[par ^ 1][i], (double)part);
+        fx_add(S.pint[i], (double)part, X.bad);
       }
     }
   } else {
@@ -508,44 +585,45 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       if (s < nsw) {
         const unsigned mk = X.sid[s];
         const int i = (int)(mk & IMASK);
-        const double coef = s < X.nslot ? sc * S.gdv[i] * S.pacc[par][i] : 0.0;
-        slot_sweep<NC>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+        const double coef = s < X.nslot ? sc * S.gdv[i] * S.pf[par][i] : 0.0;
+        slot_sweep<ZH>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
                        [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
       }
     }
-    project<Vr>(S, X, C, io, par ^ 1);
+    project<Vr>(S, X, C, io);
   }
   __syncthreads();
 }
 
+// Mirror the thread's planes into LDS (the caller places a barrier before
+// they are read).
 template <class Vr>
-__device__ __forceinline__ void clear_proj(Smem<Vr>& S, int buf) {
-  for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::L::NT) S.pacc[buf][i] = 0.0;
-}
-
-// Mirror the column into LDS (the caller places a barrier before it is read).
-template <class Vr>
-__device__ __forceinline__ void mirror(Smem<Vr>& S, const Ctx<Vr>& X, const typename Vr::T (&v)[Vr::NC]) {
+__device__ __forceinline__ void mirror(Smem<Vr>& S, const Ctx<Vr>& X, const typename Vr::T (&v)[Vr::ZH]) {
   using L = typename Vr::L;
   if (X.active) {
-    const int base = L::at(X.cx, X.cy, 0);
 #pragma unroll
-    for (int z = 0; z < Vr::NC; ++z) S.tl[base + z * L::PL] = v[z];
+    for (int z = 0; z < Vr::ZH; ++z)
+      S.tl[X.bown + z * L::PL] = v[z];
   }
 }
 
+// cur = cw w_q (the unit vector at the node scaled by cw), prv = 0; mirrored;
+// its projections in S.pf[0].
 template <class Vr>
-__device__ __forceinline__ void load_unit(Smem<Vr>& S, Ctx<Vr>& X, typename Vr::T (&cur)[Vr::NC],
-                                          typename Vr::T (&prv)[Vr::NC]) {
+__device__ __forceinline__ void load_unit(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
+                                          typename Vr::T (&cur)[Vr::ZH], typename Vr::T (&prv)[Vr::ZH],
+                                          double cw = 1.0) {
   using T = typename Vr::T;
-  constexpr int NC = Vr::NC;
-  constexpr int m = NC / 2;
+  constexpr int m = Vr::MH;
 #pragma unroll
-  for (int z = 0; z < NC; ++z) {
-    cur[z] = (X.active && X.cx == m && X.cy == m && z == m) ? (T)1 : (T)0;
+  for (int z = 0; z < Vr::ZH; ++z) {
+    cur[z] = (X.active && X.cx == m && X.cy == m && z == m) ? (T)cw : (T)0;
     prv[z] = (T)0;
   }
   mirror<Vr>(S, X, cur);
+  project<Vr>(S, X, C, cur);
+  __syncthreads();
+  finish_proj<Vr>(S, 1);   // S.pf[0]
   __syncthreads();
 }
 
@@ -556,8 +634,9 @@ __device__ __forceinline__ void stencil_coefs(const CellDev& C, T* ck) {
   for (int k = 0; k <= SQ_FDM; ++k) ck[k] = sizeof(T) == 8 ? (T)C.ck[k] : (T)C.ckf[k];
 }
 
-// Block sums of two values; red is double-buffered by the caller (the next
-// use of the same buffer is separated by at least one more barrier).
+// Block sums of two values in a fixed order; red is double-buffered by the
+// caller (the next use of the same buffer is separated by at least one more
+// barrier).
 template <int NW>
 __device__ __forceinline__ void block_sum2_db(double& a, double& b, double* red) {
   a = warp_sum(a);
@@ -578,34 +657,62 @@ __device__ __forceinline__ void block_sum2_db(double& a, double& b, double* red)
   b = sb;
 }
 
+// Nodes of one launch: one workgroup per node, or (PERSIST) a persistent
+// grid whose workgroups take node indices from the counter until the list
+// is exhausted.  f(g, cell) processes the node (one call site, so that the
+// node body is inlined: a called function would keep its arrays in scratch
+// memory); the loop places a barrier before the next node's prologue.
+// (a template parameter: a loop around the node body changes the register
+// allocation of the whole kernel, so the one-node form has no loop)
+template <class Vr, bool PERSIST, class F>
+__device__ __forceinline__ void for_nodes(Smem<Vr>& S, const long long* items, const int* item_cell,
+                                          long long nitems, unsigned* counter, F f) {
+  if constexpr (!PERSIST) {
+    f(items[blockIdx.x], item_cell[blockIdx.x]);
+  } else {
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) S.item = atomicAdd(counter, 1u);
+      __syncthreads();
+      const long long it = (long long)S.item;
+      if (it >= nitems) break;
+      f(items[it], item_cell[it]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Gram matrix of the projectors over the cube, G_IJ = <chi_I, chi_J> for
 // I <= J, restricted to the pairs whose chords share a plane on some column
-// (every other entry is zero).  Built once per node by the Lanczos pass from
-// the same per-column chords and weights the sweeps use, and stored for the
-// moments and stress passes.  A cube with more than SQ_GRAM_MAX such pairs
-// gets the count -1, and its steps take two sweeps (projector terms, then
-// projections).  Uses the cube buffer as scratch; the caller clears it
+// (every other entry is zero).  Built once per node at set-up from the same
+// chords and weights the sweeps use, and stored for the recurrence kernels,
+// which hold the entries in registers.  A cube with more than GCAP such
+// pairs gets the count -1, and its steps take two sweeps (projector terms,
+// then projections).  The entries are exact integer sums of the per-point
+// products (rounded to 2^-81), so they do not depend on how the cube is
+// split among threads.  Uses the cube buffer as scratch; the caller clears it
 // afterwards.
 // ---------------------------------------------------------------------------
 template <class Vr>
-__device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C) {
-  using L = typename Vr::L;
-  constexpr int NC = Vr::NC;
+__device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C, unsigned* err) {
+  constexpr int ZH = Vr::ZH;
   constexpr int NI = Vr::NIMG;
   constexpr int NWD = Vr::NWD;
-  constexpr int NT = L::NT;
+  constexpr int NT = Vr::NT;
+  constexpr int CAP = Vr::GCAP;
   constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
   static_assert(sizeof(S.tl) >= Vr::GSCR, "Gram scratch");
-  unsigned* bm = reinterpret_cast<unsigned*>(S.tl);   // [NI][NWD] pairs present
-  int* rs = reinterpret_cast<int*>(bm + NI * NWD);     // [NI + 1] first entry of each row
-  unsigned* sl = reinterpret_cast<unsigned*>(rs + NI + 1);   // [KC][NT] slot words
+  unsigned* bm = reinterpret_cast<unsigned*>(S.tl);            // [NI][NWD] pairs present
+  int* rs = reinterpret_cast<int*>(bm + NI * NWD);              // [NI + 1] first entry of each row
+  unsigned* sl = reinterpret_cast<unsigned*>(rs + NI + 1);      // [KC][NT] slot words
+  unsigned long long* ga = reinterpret_cast<unsigned long long*>(
+      reinterpret_cast<char*>(S.tl) + ((4 * ((size_t)NI * NWD + NI + 1 + (size_t)Vr::KC * NT) + 15) & ~(size_t)15));
   const int tid = threadIdx.x;
   for (int k = tid; k < NI * NWD; k += NT) bm[k] = 0u;
 #pragma unroll
   for (int s = 0; s < Vr::KC; ++s) sl[s * NT + tid] = X.sid[s];
   __syncthreads();
-  // pairs of this column's slots (image indices increase with the slot)
+  // pairs of this thread's slots (image indices increase with the slot)
   if (X.active) {
     for (int s = 0; s < X.nslot; ++s) {
       const unsigned a = sl[s * NT + tid];
@@ -619,11 +726,11 @@ __device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C) {
     }
   }
   __syncthreads();
-  if (tid < NI) {
+  for (int r = tid; r < NI; r += NT) {   // row counts (every row, whatever the block size)
     int c = 0;
 #pragma unroll
-    for (int w = 0; w < NWD; ++w) c += __popc(bm[tid * NWD + w]);
-    rs[tid] = c;
+    for (int w = 0; w < NWD; ++w) c += __popc(bm[r * NWD + w]);
+    rs[r] = c;
   }
   __syncthreads();
   if (tid < 64) {   // exclusive scan of the row counts by wave 0
@@ -653,34 +760,42 @@ __device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C) {
   }
   __syncthreads();
   const int total = S.ngram;
-  const bool fits = total <= SQ_GRAM_MAX;
+  const bool fits = total <= CAP;
   if (fits)
-    for (int e = tid; e < total; e += NT) S.gval[e] = 0.0;
+    for (int e = tid; e < 2 * total; e += NT) ga[e] = 0ull;
   __syncthreads();
-  // column sums of chi_I chi_J over the shared planes
+  // column sums of chi_I chi_J over the shared planes, point by point
   if (X.active && fits) {
-    constexpr int m = NC / 2;
+    constexpr int m = Vr::MH;
     const double h = C.h;
     for (int s = 0; s < X.nslot; ++s) {
       const unsigned a = sl[s * NT + tid];
       const int i = (int)(a & IMASK);
       const double wi = exp(-sq_sum2(node_coord(X.q0 + X.cx - m, h, S.ix[i]),
-                                     node_coord(X.q1 + X.cy - m, h, S.iy[i])) * S.i2s[i]) * S.e0[i];
+                                     node_coord(X.q1 + X.cy - m, h, S.iy[i])) * S.i2s[i]) *
+                        S.e0[i];
       for (int s2 = s; s2 < X.nslot; ++s2) {
         const unsigned b = sl[s2 * NT + tid];
         if ((a & b & ~IMASK) == 0u) continue;
         const int j = (int)(b & IMASK);
         const double wj = exp(-sq_sum2(node_coord(X.q0 + X.cx - m, h, S.ix[j]),
-                                       node_coord(X.q1 + X.cy - m, h, S.iy[j])) * S.i2s[j]) * S.e0[j];
-        double ai = wi, ri = S.r0[i], aj = wj, rj = S.r0[j], sum = 0.0;
+                                       node_coord(X.q1 + X.cy - m, h, S.iy[j])) * S.i2s[j]) *
+                          S.e0[j];
+        double ai = wi, ri = S.r0[i], aj = wj, rj = S.r0[j];
         const double qi = S.cq[i], qj = S.cq[j];
-        unsigned mk = a & b;
+        long long shi = 0, slo = 0;
+        unsigned mk = a & b & ~IMASK;
 #pragma unroll
-        for (int z = 0; z < NC; ++z) {
+        for (int z = 0; z < ZH; ++z) {
           unsigned nm;
           const bool on = __builtin_add_overflow(mk, mk, &nm);
           mk = nm;
-          sum += on ? ai * aj : 0.0;
+          if (on) {
+            long long th, tlw;
+            fx_split(ai * aj, th, tlw);
+            shi += th;
+            slo += tlw;
+          }
           ai *= ri;
           ri *= qi;
           aj *= rj;
@@ -689,8 +804,29 @@ __device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C) {
         const int jw = j >> 5;
         int idx = rs[i] + __popc(bm[i * NWD + jw] & ((1u << (j & 31)) - 1u));
         for (int w = 0; w < jw; ++w) idx += __popc(bm[i * NWD + w]);
-        atomicAdd(&S.gval[idx], sum);
-        S.gidx[idx] = (unsigned)i | ((unsigned)j << 16);
+        if (idx >= 0 && idx < total) {
+          atomicAdd(&ga[2 * idx], (unsigned long long)shi);
+          atomicAdd(&ga[2 * idx + 1], (unsigned long long)slo);
+        } else {
+          atomicOr(err, SQ_ERR_IMAGES);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // entry order (I, J): rows in order, J increasing within a row
+  if (fits) {
+    unsigned* gidx = reinterpret_cast<unsigned*>(rs + NI + 1);   // reuses the slot words
+    for (int r = tid; r < NI; r += NT) {
+      int e = rs[r];
+      for (int w = 0; w < NWD; ++w) {
+        unsigned bits = bm[r * NWD + w];
+        while (bits) {
+          const int b = __ffs(bits) - 1;
+          bits &= bits - 1u;
+          if (e < total) gidx[e] = (unsigned)r | ((unsigned)(32 * w + b) << 16);
+          ++e;
+        }
       }
     }
   }
@@ -699,24 +835,37 @@ __device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C) {
 }
 
 template <class Vr>
-__device__ __forceinline__ void gram_store(const Smem<Vr>& S, const PlanDev& P, long long g) {
-  const int ng = S.ngram;
-  for (int e = threadIdx.x; e < ng; e += Vr::L::NT) {
-    P.gval[g * SQ_GRAM_MAX + e] = S.gval[e];
-    P.gidx[g * SQ_GRAM_MAX + e] = S.gidx[e];
+__device__ __forceinline__ void gram_store(Smem<Vr>& S, const PlanDev& P, long long g) {
+  constexpr int NI = Vr::NIMG;
+  constexpr int NWD = Vr::NWD;
+  const int ng = min(max(S.ngram, -1), Vr::GCAP);
+  const int* rs = reinterpret_cast<const int*>(reinterpret_cast<const unsigned*>(S.tl) + NI * NWD);
+  const unsigned* gidx = reinterpret_cast<const unsigned*>(rs + NI + 1);
+  const unsigned long long* ga = reinterpret_cast<const unsigned long long*>(
+      reinterpret_cast<const char*>(S.tl) +
+      ((4 * ((size_t)NI * NWD + NI + 1 + (size_t)Vr::KC * Vr::NT) + 15) & ~(size_t)15));
+  for (int e = threadIdx.x; e < ng; e += Vr::NT) {
+    P.gval[g * SQ_GRAM_MAX + e] = fx_join((long long)ga[2 * e], (long long)ga[2 * e + 1]);
+    P.gidx[g * SQ_GRAM_MAX + e] = gidx[e];
   }
   if (threadIdx.x == 0) P.gn[g] = ng;
 }
 
-// (the caller places a barrier before the entries are read)
+// The node's stored Gram entries: thread t uses entries t + e NT at every
+// step.  A count over the variant's capacity (the host never launches such
+// a node on the single-sweep form) uses none.
 template <class Vr>
-__device__ __forceinline__ void gram_load(Smem<Vr>& S, const PlanDev& P, long long g) {
-  const int ng = min(max(P.gn[g], -1), SQ_GRAM_MAX);
-  for (int e = threadIdx.x; e < ng; e += Vr::L::NT) {
-    S.gval[e] = P.gval[g * SQ_GRAM_MAX + e];
-    S.gidx[e] = P.gidx[g * SQ_GRAM_MAX + e];
-  }
-  if (threadIdx.x == 0) S.ngram = ng;
+__device__ __forceinline__ void gram_load(Ctx<Vr>& X, const PlanDev& P, long long g) {
+  const int ng = P.gn[g];
+  X.ngram = (ng >= 0 && ng <= Vr::GCAP) ? ng : 0;
+  X.gvp = P.gval + g * SQ_GRAM_MAX;
+  X.gip = P.gidx + g * SQ_GRAM_MAX;
+}
+
+// End of a node: report fixed-point terms that were out of range.
+template <class Vr>
+__device__ __forceinline__ void node_epilogue(const Ctx<Vr>& X, unsigned* err) {
+  if (X.bad) atomicOr(err, SQ_ERR_RANGE);
 }
 
 // ---------------------------------------------------------------------------
@@ -727,19 +876,19 @@ __device__ __forceinline__ void gram_load(Smem<Vr>& S, const PlanDev& P, long lo
 // v_{k+1} is in B (and S.tl) unless the recursion stopped.
 template <class Vr, bool FUSED>
 __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
-                                             const double (&A)[Vr::NC], double (&B)[Vr::NC],
+                                             const double (&A)[Vr::ZH], double (&B)[Vr::ZH],
                                              const double* ck, int k, double& bprev, double& tol,
                                              double* lan) {
-  constexpr int NC = Vr::NC;
-  constexpr int NW = Vr::L::NW;
+  constexpr int ZH = Vr::ZH;
+  constexpr int NW = Vr::NW;
   apply_step<Vr, FUSED>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
   double a = 0.0, dum = 0.0;
 #pragma unroll
-  for (int z = 0; z < NC; ++z) a += A[z] * B[z];
+  for (int z = 0; z < ZH; ++z) a += A[z] * B[z];
   block_sum2_db<NW>(a, dum, S.red[0]);
   double b = 0.0;
 #pragma unroll
-  for (int z = 0; z < NC; ++z) {
+  for (int z = 0; z < ZH; ++z) {
     B[z] -= a * A[z];
     b += B[z] * B[z];
   }
@@ -753,55 +902,52 @@ __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const Cell
   if (b < tol) return false;
   const double ib = 1.0 / b;
 #pragma unroll
-  for (int z = 0; z < NC; ++z) B[z] *= ib;
+  for (int z = 0; z < ZH; ++z) B[z] *= ib;
   mirror<Vr>(S, X, B);
   // projections of v_{k+1} = (H v_k - beta v_{k-1} - a v_k) / b
-  const int par = k & 1;
-  for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::L::NT) {
-    S.pacc[par ^ 1][i] = (S.pacc[par ^ 1][i] - a * S.pacc[par][i]) * ib;
-    S.pacc[par][i] = 0.0;
-  }
+  finish_proj<Vr>(S, k & 1, a, ib);
   bprev = b;
   __syncthreads();
   return true;
 }
 
-template <class Vr, bool FUSED>
-__global__ void __launch_bounds__(Vr::L::NT) k_lanczos(PlanDev P, const long long* items,
-                                                        const int* item_cell) {
+template <class Vr, bool FUSED, bool PERSIST>
+__global__ void __launch_bounds__(Vr::NT) k_lanczos(PlanDev P, const long long* items,
+                                                     const int* item_cell, long long nitems,
+                                                     unsigned* counter) {
   static_assert(sizeof(typename Vr::T) == 8, "Lanczos runs in FP64");
-  constexpr int NC = Vr::NC;
+  constexpr int ZH = Vr::ZH;
   __shared__ Smem<Vr> S;
-  const long long g = items[blockIdx.x];
-  const CellDev& C = P.cells[item_cell[blockIdx.x]];
-  const long long q = g - C.node_base;
-  Ctx<Vr> X;
-  node_prologue<Vr>(C, q, 0.0, S, X, P.err);
-  if constexpr (FUSED) gram_load<Vr>(S, P, g);
-  double ck[SQ_FDM + 1];
-  stencil_coefs<double>(C, ck);
-  double A[NC], B[NC];
-  load_unit<Vr>(S, X, A, B);
-  project<Vr>(S, X, C, A, 0);
-  __syncthreads();
-  double bprev = 0.0, tol = 0.0;
-  int steps = 0;
-  double* lan = P.lan + g * (2 * SQ_KL_MAX);
-  for (int k = 0; k < C.K; k += 2) {
-    steps = k + 1;
-    if (!lanczos_step<Vr, FUSED>(S, X, C, A, B, ck, k, bprev, tol, lan)) break;
-    if (k + 1 >= C.K) break;
-    steps = k + 2;
-    if (!lanczos_step<Vr, FUSED>(S, X, C, B, A, ck, k + 1, bprev, tol, lan)) break;
-  }
-  if (threadIdx.x == 0) P.lan_steps[g] = steps;
+  for_nodes<Vr, PERSIST>(S, items, item_cell, nitems, counter, [&](long long g, int ci) __attribute__((always_inline)) {
+    const CellDev& C = P.cells[ci];
+    const long long q = g - C.node_base;
+    Ctx<Vr> X;
+    node_prologue<Vr>(C, q, 0.0, S, X, P.err);
+    if constexpr (FUSED) gram_load<Vr>(X, P, g);
+    double ck[SQ_FDM + 1];
+    stencil_coefs<double>(C, ck);
+    double A[ZH], B[ZH];
+    load_unit<Vr>(S, X, C, A, B);
+    double bprev = 0.0, tol = 0.0;
+    int steps = 0;
+    double* lan = P.lan + g * (2 * SQ_KL_MAX);
+    for (int k = 0; k < C.K; k += 2) {
+      steps = k + 1;
+      if (!lanczos_step<Vr, FUSED>(S, X, C, A, B, ck, k, bprev, tol, lan)) break;
+      if (k + 1 >= C.K) break;
+      steps = k + 2;
+      if (!lanczos_step<Vr, FUSED>(S, X, C, B, A, ck, k + 1, bprev, tol, lan)) break;
+    }
+    if (threadIdx.x == 0) P.lan_steps[g] = steps;
+    node_epilogue<Vr>(X, P.err);
+  });
 }
 
 // Set-up pass: the Gram matrix of every node's projectors (count -1 when it
-// exceeds SQ_GRAM_MAX entries; such nodes are launched with FUSED = false).
+// exceeds the capacity; such nodes are launched with FUSED = false).
 template <class Vr>
-__global__ void __launch_bounds__(Vr::L::NT) k_gram(PlanDev P, const long long* items,
-                                                     const int* item_cell) {
+__global__ void __launch_bounds__(Vr::NT) k_gram(PlanDev P, const long long* items,
+                                                  const int* item_cell) {
   static_assert(sizeof(typename Vr::T) == 8, "the Gram build runs in FP64");
   __shared__ Smem<Vr> S;
   const long long g = items[blockIdx.x];
@@ -809,7 +955,7 @@ __global__ void __launch_bounds__(Vr::L::NT) k_gram(PlanDev P, const long long* 
   const long long q = g - C.node_base;
   Ctx<Vr> X;
   node_prologue<Vr>(C, q, 0.0, S, X, P.err);
-  gram_build<Vr>(S, X, C);
+  gram_build<Vr>(S, X, C, P.err);
   gram_store<Vr>(S, P, g);
 }
 
@@ -819,344 +965,351 @@ __global__ void __launch_bounds__(Vr::L::NT) k_gram(PlanDev P, const long long* 
 //   rho^{2k} = 2 <t^k, t^k> - rho^0,  rho^{2k+1} = 2 <t^{k+1}, t^k> - rho^1
 // (Hhat_q is symmetric, T_{a+b} + T_{|a-b|} = 2 T_a T_b).
 // ---------------------------------------------------------------------------
-template <class Vr, bool FUSED>
-__global__ void __launch_bounds__(Vr::L::NT) k_moments(PlanDev P, const long long* items,
-                                                        const int* item_cell) {
+template <class Vr, bool FUSED, bool PERSIST>
+__global__ void __launch_bounds__(Vr::NT) k_moments(PlanDev P, const long long* items,
+                                                     const int* item_cell, long long nitems,
+                                                     unsigned* counter) {
   using T = typename Vr::T;
-  constexpr int NC = Vr::NC;
-  constexpr int NW = Vr::L::NW;
+  constexpr int ZH = Vr::ZH;
+  constexpr int NW = Vr::NW;
   __shared__ Smem<Vr> S;
-  const long long g = items[blockIdx.x];
-  const CellDev& C = P.cells[item_cell[blockIdx.x]];
-  const long long q = g - C.node_base;
-  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
-  Ctx<Vr> X;
-  node_prologue<Vr>(C, q, chi, S, X, P.err);
-  if constexpr (FUSED) gram_load<Vr>(S, P, g);
-  T ck[SQ_FDM + 1];
-  stencil_coefs<T>(C, ck);
-  T A[NC], B[NC];
-  load_unit<Vr>(S, X, A, B);
-  project<Vr>(S, X, C, A, 0);
-  __syncthreads();
-  double* mom = P.mom + g * P.mstride;
-  const int npl = C.npl;
-  const int kmax = (npl + 1) / 2;
-  double rho1 = 0.0;
-  bool bad = false;
-  if (threadIdx.x == 0) mom[0] = 1.0;
-  // t^{k+1} from t^k (cur) and t^{k-1} (io); then rho^{2k+1}, rho^{2k+2}
-  auto step = [&](const T (&cur)[NC], T (&io)[NC], int k) {
-    apply_step<Vr, FUSED>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, k == 0 ? (T)0 : (T)1,
-                   k & 1);
-    double sq = 0.0, cr = 0.0;
+  for_nodes<Vr, PERSIST>(S, items, item_cell, nitems, counter, [&](long long g, int ci) __attribute__((always_inline)) {
+    const CellDev& C = P.cells[ci];
+    const long long q = g - C.node_base;
+    const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+    Ctx<Vr> X;
+    node_prologue<Vr>(C, q, chi, S, X, P.err);
+    if constexpr (FUSED) gram_load<Vr>(X, P, g);
+    T ck[SQ_FDM + 1];
+    stencil_coefs<T>(C, ck);
+    T A[ZH], B[ZH];
+    load_unit<Vr>(S, X, C, A, B);
+    double* mom = P.mom + g * P.mstride;
+    const int npl = C.npl;
+    const int kmax = (npl + 1) / 2;
+    double rho1 = 0.0;
+    bool bad = false;
+    if (threadIdx.x == 0) mom[0] = 1.0;
+    // t^{k+1} from t^k (cur) and t^{k-1} (io); then rho^{2k+1}, rho^{2k+2}
+    auto step = [&](const T (&cur)[ZH], T (&io)[ZH], int k) {
+      apply_step<Vr, FUSED>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta,
+                            k == 0 ? (T)0 : (T)1, k & 1);
+      double sq = 0.0, cr = 0.0;
 #pragma unroll
-    for (int z = 0; z < NC; ++z) {
-      const double a = (double)io[z], b = (double)cur[z];
-      sq += a * a;
-      cr += a * b;
+      for (int z = 0; z < ZH; ++z) {
+        const double a = (double)io[z], b = (double)cur[z];
+        sq += a * a;
+        cr += a * b;
+      }
+      mirror<Vr>(S, X, io);
+      finish_proj<Vr>(S, k & 1);
+      block_sum2_db<NW>(sq, cr, S.red[k & 1]);
+      if (k == 0) rho1 = cr;
+      const int j1 = 2 * k + 1, j2 = 2 * k + 2;
+      const double r1 = (k == 0) ? cr : 2.0 * cr - rho1;
+      const double r2 = 2.0 * sq - 1.0;
+      // |rho^j| <= 1 when the bounds hold: 1e-6 slack for FP64 rounding, 1e-4
+      // for FP32 vectors (their rounding reaches 1e-6 near |rho^j| = 1)
+      constexpr double btol = sizeof(T) == 8 ? 1e-6 : 1e-4;
+      if (fabs(r1) > 1.0 + btol || (j2 <= npl && fabs(r2) > 1.0 + btol) || !(r1 == r1)) bad = true;
+      if (threadIdx.x == 0) {
+        mom[j1] = r1;
+        if (j2 <= npl) mom[j2] = r2;
+      }
+    };
+    for (int k = 0; k < kmax; k += 2) {
+      step(A, B, k);
+      if (k + 1 < kmax) step(B, A, k + 1);
     }
-    mirror<Vr>(S, X, io);
-    clear_proj<Vr>(S, k & 1);
-    block_sum2_db<NW>(sq, cr, S.red[k & 1]);
-    if (k == 0) rho1 = cr;
-    const int j1 = 2 * k + 1, j2 = 2 * k + 2;
-    const double r1 = (k == 0) ? cr : 2.0 * cr - rho1;
-    const double r2 = 2.0 * sq - 1.0;
-    if (fabs(r1) > 1.0 + 1e-4 || (j2 <= npl && fabs(r2) > 1.0 + 1e-4) || !(r1 == r1)) bad = true;
-    if (threadIdx.x == 0) {
-      mom[j1] = r1;
-      if (j2 <= npl) mom[j2] = r2;
-    }
-  };
-  for (int k = 0; k < kmax; k += 2) {
-    step(A, B, k);
-    if (k + 1 < kmax) step(B, A, k + 1);
-  }
-  if (bad && threadIdx.x == 0) atomicOr(P.err, SQ_ERR_BOUNDS);
+    if (bad && threadIdx.x == 0) atomicOr(P.err, SQ_ERR_BOUNDS);
+    node_epilogue<Vr>(X, P.err);
+  });
 }
 
 // ---------------------------------------------------------------------------
 // Stress pass: recurrence again with the coefficients known, the DM column
-// d_q = sum'_j c_q^j t^j accumulated in FP64, then the kinetic functional
+// d_q = sum'_j c_q^j t^j, then the kinetic functional
 // K_ab = 2 (grad_a grad_b d_q)_q and the nonlocal functional
 // N_ab = -2 sum_I gamma dV chi_I(x_q) [delta_ab chi_I^T d_q
 //        + 2 sum_y chi_I(y) (y_b - R_Ib) (grad_a d_q)(y)]   (Sec. IV)
 // ---------------------------------------------------------------------------
+// One round of the gradient along x (dir 0) or y (dir 1) of the vector
+// part, mirrored in LDS: g[z] += sum_k w_k (part(+k) - part(-k)) on the own
+// planes (unscaled by 1/h).  Two barriers.
 template <class Vr>
-__device__ __forceinline__ void grad_xy_round(Smem<Vr>& S, Ctx<Vr>& X,
-                                              const typename Vr::T (&part)[Vr::NC],
-                                              double (&gx)[Vr::NC], double (&gy)[Vr::NC],
-                                              const double* w) {
-  constexpr int NC = Vr::NC;
+__device__ __forceinline__ void grad_round(Smem<Vr>& S, Ctx<Vr>& X, const typename Vr::T (&part)[Vr::ZH],
+                                           double (&g)[Vr::ZH], const double* w, int dir) {
   using T = typename Vr::T;
   using L = typename Vr::L;
-  const int base = L::at(X.cx, X.cy, 0);
   mirror<Vr>(S, X, part);
   __syncthreads();
   if (X.active) {
-    const int cx = X.cx, cy = X.cy;
+    const int st = dir == 0 ? 1 : L::RS;
+    const int pos = dir == 0 ? X.cx : X.cy;
 #pragma unroll
-    for (int z = 0; z < NC; ++z) {
-      const T* pc = S.tl + base + z * L::PL;
-      double ax = 0.0, ay = 0.0;
+    for (int z = 0; z < Vr::ZH; ++z) {
+      const T* pc = S.tl + X.bown + z * L::PL;
+      double a = 0.0;
 #pragma unroll
       for (int k = 1; k <= SQ_FDM; ++k) {
-        if constexpr (L::RS > NC) {
-          ax += w[k] * ((double)pc[k] - (double)pc[-k]);
-          ay += w[k] * ((double)pc[k * L::RS] - (double)pc[-k * L::RS]);
+        if constexpr (L::RS > Vr::NC) {
+          a += w[k] * ((double)pc[k * st] - (double)pc[-k * st]);
         } else {
-          if (cx + k < NC) ax += w[k] * (double)pc[k];
-          if (cx - k >= 0) ax -= w[k] * (double)pc[-k];
-          if (cy + k < NC) ay += w[k] * (double)pc[k * L::RS];
-          if (cy - k >= 0) ay -= w[k] * (double)pc[-k * L::RS];
+          if (pos + k < Vr::NC) a += w[k] * (double)pc[k * st];
+          if (pos - k >= 0) a -= w[k] * (double)pc[-k * st];
         }
       }
-      gx[z] += ax;
-      gy[z] += ay;
+      g[z] += a;
     }
   }
   __syncthreads();
 }
 
-template <class Vr, bool FUSED>
-__global__ void __launch_bounds__(Vr::L::NT) k_stress(PlanDev P, const long long* items,
-                                                       const int* item_cell) {
-  using T = typename Vr::T;
-  using L = typename Vr::L;
-  constexpr int NC = Vr::NC;
-  constexpr int NC2 = NC * NC;
-  constexpr int m = L::MH;
-  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
-  __shared__ Smem<Vr> S;
-  const long long g = items[blockIdx.x];
-  const CellDev& C = P.cells[item_cell[blockIdx.x]];
-  const long long q = g - C.node_base;
-  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
-  const double* coef = P.coef + g * P.mstride;
-  Ctx<Vr> X;
-  node_prologue<Vr>(C, q, chi, S, X, P.err);
-  if constexpr (FUSED) gram_load<Vr>(S, P, g);
-  T ck[SQ_FDM + 1];
-  stencil_coefs<T>(C, ck);
-  T A[NC], B[NC];
-  double d[NC];
-  const int npl = C.npl;
-  if constexpr (sizeof(T) == 8) {
-    // FP64: Clenshaw's recurrence for d_q = sum'_j c_j T_j(Hhat) w_q,
-    //   b_k = c_k w + 2 Hhat b_{k+1} - b_{k+2},  k = npl-1 .. 1,
-    //   b_npl = c_npl w,  b_{npl+1} = 0,  d_q = c_0 w / 2 + Hhat b_1 - b_2,
-    // the same npl applications as the forward recurrence but no separate
-    // accumulator for d_q (registers)
-    load_unit<Vr>(S, X, A, B);
-    const T cn = (T)coef[npl];
+// Gradient along z of the FP64 column d (registers; neighbours outside the
+// cube dropped).
+template <class Vr>
+__device__ __forceinline__ void grad_z(const Ctx<Vr>& X, const double (&d)[Vr::ZH], double (&g)[Vr::ZH],
+                                       const double* w, double ih) {
+  constexpr int ZH = Vr::ZH;
 #pragma unroll
-    for (int z = 0; z < NC; ++z) A[z] *= cn;
-    mirror<Vr>(S, X, A);
-    __syncthreads();
-    project<Vr>(S, X, C, A, 0);
-    __syncthreads();
-    // step j computes b_k, k = npl - 1 - j, from b_{k+1} (cur) and b_{k+2}
-    // (io); the last one (k = 0) forms d_q
-    auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
-      const int k = npl - 1 - j;
-      apply_step<Vr, FUSED>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, (T)1, j & 1,
-                            k == 0 ? 0.5 * coef[0] : coef[k]);
-      mirror<Vr>(S, X, io);
-      clear_proj<Vr>(S, j & 1);
-      __syncthreads();
-    };
-    for (int j = 0; j < npl; j += 2) {
-      step(A, B, j);
-      if (j + 1 < npl) step(B, A, j + 1);
-    }
-    const bool in_b = (npl & 1) != 0;
-#pragma unroll
-    for (int z = 0; z < NC; ++z) d[z] = (double)(in_b ? B[z] : A[z]);
-  } else {
-    // FP32 vectors: forward recurrence t^{j+1} = 2 Hhat t^j - t^{j-1} with
-    // d_q = sum'_j c_j t^j accumulated in FP64
-    load_unit<Vr>(S, X, A, B);
-    project<Vr>(S, X, C, A, 0);
-    __syncthreads();
-    const double c0h = 0.5 * coef[0];
-#pragma unroll
-    for (int z = 0; z < NC; ++z) d[z] = c0h * (double)A[z];
-    auto step = [&](const T (&cur)[NC], T (&io)[NC], int j) {
-      apply_step<Vr, FUSED>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta,
-                            j == 0 ? (T)0 : (T)1, j & 1);
-      const double cj = coef[j + 1];
-#pragma unroll
-      for (int z = 0; z < NC; ++z) d[z] += cj * (double)io[z];
-      mirror<Vr>(S, X, io);
-      clear_proj<Vr>(S, j & 1);
-      __syncthreads();
-    };
-    for (int j = 0; j < npl; j += 2) {
-      step(A, B, j);
-      if (j + 1 < npl) step(B, A, j + 1);
-    }
-  }
-
-  // ---- gradients of d along x, y (LDS, FP64 via hi/lo rounds) and z ----
-  const double ih = 1.0 / C.h;
-  double w[SQ_FDM + 1];
-#pragma unroll
-  for (int k = 0; k <= SQ_FDM; ++k) w[k] = C.c1[k];
-  double gx[NC], gy[NC], gz[NC];
-#pragma unroll
-  for (int z = 0; z < NC; ++z) {
-    gx[z] = 0.0;
-    gy[z] = 0.0;
+  for (int z = 0; z < ZH; ++z) {
     double a = 0.0;
 #pragma unroll
     for (int k = 1; k <= SQ_FDM; ++k) {
-      if (z + k < NC) a += w[k] * d[z + k];
-      if (z - k >= 0) a -= w[k] * d[z - k];
+      double up = 0.0, dn = 0.0;
+      if (z + k < ZH) up = d[z + k];
+      if (z - k >= 0) dn = d[z - k];
+      a += w[k] * (up - dn);
     }
-    gz[z] = a * ih;
+    g[z] = X.active ? a * ih : 0.0;
   }
-  {
-    T hi[NC];
-#pragma unroll
-    for (int z = 0; z < NC; ++z) hi[z] = (T)d[z];
-    grad_xy_round<Vr>(S, X, hi, gx, gy, w);
-    if constexpr (sizeof(T) < sizeof(double)) {
-#pragma unroll
-      for (int z = 0; z < NC; ++z) hi[z] = (T)(d[z] - (double)hi[z]);
-      grad_xy_round<Vr>(S, X, hi, gx, gy, w);
-    }
-#pragma unroll
-    for (int z = 0; z < NC; ++z) {
-      gx[z] *= ih;
-      gy[z] *= ih;
-    }
-  }
+}
 
-  // ---- kinetic functional from the plane z = m and the centre column ----
-  double* plane = reinterpret_cast<double*>(S.tl);   // 3 * NC2 + 3 * NC doubles
-  static_assert(sizeof(T) * L::SIZE >= sizeof(double) * (3 * NC2 + 3 * NC), "plane");
-  if (X.active) {
-    plane[X.col] = gx[m];
-    plane[NC2 + X.col] = gy[m];
-    plane[2 * NC2 + X.col] = gz[m];
-    if (X.cx == m && X.cy == m) {
-#pragma unroll
-      for (int z = 0; z < NC; ++z) {
-        plane[3 * NC2 + z] = gx[z];
-        plane[3 * NC2 + NC + z] = gy[z];
-        plane[3 * NC2 + 2 * NC + z] = gz[z];
-      }
-    }
-  }
-  // ---- near images: projector nonzero at the node itself ----
-  if (X.active && X.cx == m && X.cy == m) {
-    int nn = 0;
-#pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) {
-      if (s < X.nslot) {
-        const unsigned mk = X.sid[s];
-        const int i = (int)(mk & IMASK);
-        if (mk & (0x80000000u >> m)) {
-          if (nn < Vr::NEAR) {
-            S.near_img[nn] = i;
-            const double dx = node_coord(X.q0, C.h, S.ix[i]);
-            const double dy = node_coord(X.q1, C.h, S.iy[i]);
-            const double dz = node_coord(X.q2, C.h, S.iz[i]);
-            S.near_chi[nn] = exp(-sq_add(sq_sum2(dx, dy), dz) * S.i2s[i]);
-          } else {
-            atomicOr(P.err, SQ_ERR_NEAR);
-          }
-          ++nn;
-        }
-      }
-    }
-    S.nnear = nn < Vr::NEAR ? nn : Vr::NEAR;
-  }
-  for (int i = threadIdx.x; i < Vr::NEAR * 10; i += L::NT) (&S.nsum[0][0])[i] = 0.0;
-  __syncthreads();
-
-  double* rec = P.rec + g * SQ_REC;
-  if (threadIdx.x == 0) {
-    const double* px = plane;
-    const double* py = plane + NC2;
-    const double* pz = plane + 2 * NC2;
-    const double* cxg = plane + 3 * NC2;
-    // (grad_a G_b)(c) = (1/h) sum_k w_k (G_b(c + k e_a) - G_b(c - k e_a))
-    for (int b = 0; b < 3; ++b) {
-      const double* pb = b == 0 ? px : (b == 1 ? py : pz);
-      const double* cb = cxg + b * NC;
-      double kx = 0.0, ky = 0.0, kz = 0.0;
-      for (int k = 1; k <= SQ_FDM; ++k) {
-        if (k > m) break;
-        kx += w[k] * (pb[m * NC + m + k] - pb[m * NC + m - k]);
-        ky += w[k] * (pb[(m + k) * NC + m] - pb[(m - k) * NC + m]);
-        kz += w[k] * (cb[m + k] - cb[m - k]);
-      }
-      rec[2 + 0 * 3 + b] = 2.0 * kx * ih;
-      rec[2 + 1 * 3 + b] = 2.0 * ky * ih;
-      rec[2 + 2 * 3 + b] = 2.0 * kz * ih;
-    }
-  }
-
-  // ---- nonlocal sums over the support of every near image ----
+// Nonlocal sums over the supports of the near images, for the thread's
+// slots whose image is near: DIR = -1: sum chi d (into term 0); DIR = a:
+// sum chi (y_b - R_b) (grad_a d) for b = 0..2 (terms 1 + 3a + b).
+template <class Vr, int DIR>
+__device__ __forceinline__ void near_sums(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
+                                          const double (&v)[Vr::ZH]) {
+  constexpr int m = Vr::MH;
+  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
   const int nnear = S.nnear;
-  if (X.active && nnear > 0) {
-    const double xc = (double)(X.q0 + X.cx - m) * C.h;
-    const double yc = (double)(X.q1 + X.cy - m) * C.h;
+  if (!X.active || nnear == 0) return;
+  const double xc = (double)(X.q0 + X.cx - m) * C.h;
+  const double yc = (double)(X.q1 + X.cy - m) * C.h;
 #pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) {
-      if (s < X.nslot) {
-        const unsigned mk = X.sid[s];
-        const int i = (int)(mk & IMASK);
-        int nidx = -1;
-        for (int n = 0; n < nnear; ++n)
-          if (S.near_img[n] == i) nidx = n;
-        if (nidx >= 0) {
-          const double rx = xc - S.ix[i], ry = yc - S.iy[i];
-          double acc[10];
+  for (int s = 0; s < Vr::KC; ++s) {
+    if (s < X.nslot) {
+      const unsigned mk = X.sid[s];
+      const int i = (int)(mk & IMASK);
+      int nidx = -1;
+      for (int n = 0; n < nnear; ++n)
+        if (S.near_img[n] == i) nidx = n;
+      if (nidx >= 0) {
+        const double rx = xc - S.ix[i], ry = yc - S.iy[i];
+        double acc[3] = {0.0, 0.0, 0.0};
+        slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+                           [&](int z, bool on, double chiv) {
+                             if (on) {
+                               if constexpr (DIR < 0) {
+                                 acc[0] += chiv * v[z];
+                               } else {
+                                 const double rz = (double)(X.q2 + z - m) * C.h - S.iz[i];
+                                 const double cg = chiv * v[z];
+                                 acc[0] += cg * rx;
+                                 acc[1] += cg * ry;
+                                 acc[2] += cg * rz;
+                               }
+                             }
+                           });
+        if constexpr (DIR < 0) {
+          fx_add(S.nsum[nidx][0], acc[0], X.bad);
+        } else {
 #pragma unroll
-          for (int t = 0; t < 10; ++t) acc[t] = 0.0;
-          slot_sweep<NC>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
-                         [&](int z, bool on, double chiv) {
-                           if (on) {
-                             const double rz = (double)(X.q2 + z - m) * C.h - S.iz[i];
-                             acc[0] += chiv * d[z];
-                             const double ga[3] = {gx[z], gy[z], gz[z]};
-                             const double rb[3] = {rx, ry, rz};
-#pragma unroll
-                             for (int a = 0; a < 3; ++a)
-#pragma unroll
-                               for (int b = 0; b < 3; ++b) acc[1 + 3 * a + b] += chiv * rb[b] * ga[a];
-                           }
-                         });
-#pragma unroll
-          for (int t = 0; t < 10; ++t) atomicAdd(&S.nsum[nidx][t], acc[t]);
+          for (int b = 0; b < 3; ++b) fx_add(S.nsum[nidx][1 + 3 * DIR + b], acc[b], X.bad);
         }
       }
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double N[9], enl = 0.0;
-    for (int t = 0; t < 9; ++t) N[t] = 0.0;
-    for (int n = 0; n < nnear; ++n) {
-      const int i = S.near_img[n];
-      const double f = -2.0 * S.gdv[i] * S.near_chi[n];
-      enl -= f * S.nsum[n][0];   // 2 gamma dV chi_I(x_q) chi_I^T d_q
-      for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-          N[3 * a + b] += f * ((a == b ? S.nsum[n][0] : 0.0) + 2.0 * S.nsum[n][1 + 3 * a + b]);
+}
+
+template <class Vr, bool FUSED, bool PERSIST>
+__global__ void __launch_bounds__(Vr::NT) k_stress(PlanDev P, const long long* items,
+                                                    const int* item_cell, long long nitems,
+                                                    unsigned* counter) {
+  using T = typename Vr::T;
+  constexpr int NC = Vr::NC;
+  constexpr int ZH = Vr::ZH;
+  constexpr int NC2 = NC * NC;
+  constexpr int m = Vr::MH;
+  constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
+  __shared__ Smem<Vr> S;
+  for_nodes<Vr, PERSIST>(S, items, item_cell, nitems, counter, [&](long long g, int ci) __attribute__((always_inline)) {
+    const CellDev& C = P.cells[ci];
+    const long long q = g - C.node_base;
+    const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+    const double* coef = P.coef + g * P.mstride;
+    Ctx<Vr> X;
+    node_prologue<Vr>(C, q, chi, S, X, P.err);
+    if constexpr (FUSED) gram_load<Vr>(X, P, g);
+    T ck[SQ_FDM + 1];
+    stencil_coefs<T>(C, ck);
+    T A[ZH], B[ZH];
+    double d[ZH];
+    const int npl = C.npl;
+    if constexpr (sizeof(T) == 8) {
+      // FP64: Clenshaw's recurrence for d_q = sum'_j c_j T_j(Hhat) w_q,
+      //   b_k = c_k w + 2 Hhat b_{k+1} - b_{k+2},  k = npl-1 .. 1,
+      //   b_npl = c_npl w,  b_{npl+1} = 0,  d_q = c_0 w / 2 + Hhat b_1 - b_2,
+      // the same npl applications as the forward recurrence but no separate
+      // accumulator for d_q (registers)
+      load_unit<Vr>(S, X, C, A, B, coef[npl]);
+      // step j computes b_k, k = npl - 1 - j, from b_{k+1} (cur) and b_{k+2}
+      // (io); the last one (k = 0) forms d_q
+      auto step = [&](const T (&cur)[ZH], T (&io)[ZH], int j) {
+        const int k = npl - 1 - j;
+        apply_step<Vr, FUSED>(S, X, C, cur, io, ck, k == 0 ? 1.0 / zeta : 2.0 / zeta, (T)1, j & 1,
+                              k == 0 ? 0.5 * coef[0] : coef[k]);
+        mirror<Vr>(S, X, io);
+        finish_proj<Vr>(S, j & 1);
+        __syncthreads();
+      };
+      for (int j = 0; j < npl; j += 2) {
+        step(A, B, j);
+        if (j + 1 < npl) step(B, A, j + 1);
+      }
+      const bool in_b = (npl & 1) != 0;
+#pragma unroll
+      for (int z = 0; z < ZH; ++z) d[z] = (double)(in_b ? B[z] : A[z]);
+    } else {
+      // FP32 vectors: forward recurrence t^{j+1} = 2 Hhat t^j - t^{j-1} with
+      // d_q = sum'_j c_j t^j accumulated in FP64
+      load_unit<Vr>(S, X, C, A, B);
+      const double c0h = 0.5 * coef[0];
+#pragma unroll
+      for (int z = 0; z < ZH; ++z) d[z] = c0h * (double)A[z];
+      auto step = [&](const T (&cur)[ZH], T (&io)[ZH], int j) {
+        apply_step<Vr, FUSED>(S, X, C, cur, io, ck, j == 0 ? 1.0 / zeta : 2.0 / zeta,
+                              j == 0 ? (T)0 : (T)1, j & 1);
+        const double cj = coef[j + 1];
+#pragma unroll
+        for (int z = 0; z < ZH; ++z) d[z] += cj * (double)io[z];
+        mirror<Vr>(S, X, io);
+        finish_proj<Vr>(S, j & 1);
+        __syncthreads();
+      };
+      for (int j = 0; j < npl; j += 2) {
+        step(A, B, j);
+        if (j + 1 < npl) step(B, A, j + 1);
+      }
     }
-    for (int t = 0; t < 9; ++t) rec[11 + t] = N[t];
-    rec[20] = enl;
-  }
+
+    // ---- gradients, one direction at a time (registers: d and one
+    // gradient), the kinetic inputs on the three lines through the node,
+    // and the nonlocal sums over the near images' supports ----
+    const double ih = 1.0 / C.h;
+    double w[SQ_FDM + 1];
+#pragma unroll
+    for (int k = 0; k <= SQ_FDM; ++k) w[k] = C.c1[k];
+    // near images: projector nonzero at the node itself (found by the thread
+    // that owns the node)
+    if (X.active && X.cx == m && X.cy == m) {
+      const unsigned bit = 0x80000000u >> m;
+      int nn = 0;
+#pragma unroll
+      for (int s = 0; s < Vr::KC; ++s) {
+        if (s < X.nslot) {
+          const unsigned mk = X.sid[s];
+          const int i = (int)(mk & IMASK);
+          if (mk & bit) {
+            if (nn < Vr::NEAR) {
+              S.near_img[nn] = i;
+              const double dx = node_coord(X.q0, C.h, S.ix[i]);
+              const double dy = node_coord(X.q1, C.h, S.iy[i]);
+              const double dz = node_coord(X.q2, C.h, S.iz[i]);
+              S.near_chi[nn] = exp(-sq_add(sq_sum2(dx, dy), dz) * S.i2s[i]);
+            } else {
+              atomicOr(P.err, SQ_ERR_NEAR);
+            }
+            ++nn;
+          }
+        }
+      }
+      S.nnear = nn < Vr::NEAR ? nn : Vr::NEAR;
+    }
+    for (int i = threadIdx.x; i < Vr::NEAR * 10 * 2; i += Vr::NT) (&S.nsum[0][0][0])[i] = 0ull;
+    for (int i = threadIdx.x; i < 3 * 3 * (2 * SQ_FDM + 1); i += Vr::NT) (&S.kl[0][0][0])[i] = 0.0;
+    __syncthreads();
+    near_sums<Vr, -1>(S, X, C, d);   // chi^T d
+#pragma unroll
+    for (int dir = 0; dir < 3; ++dir) {
+      double gr[ZH];
+      if (dir < 2) {
+#pragma unroll
+        for (int z = 0; z < ZH; ++z) gr[z] = 0.0;
+        T part[ZH];
+#pragma unroll
+        for (int z = 0; z < ZH; ++z) part[z] = (T)d[z];
+        grad_round<Vr>(S, X, part, gr, w, dir);
+        if constexpr (sizeof(T) < sizeof(double)) {   // FP32 mirror: the remainder in a second round
+#pragma unroll
+          for (int z = 0; z < ZH; ++z) part[z] = (T)(d[z] - (double)part[z]);
+          grad_round<Vr>(S, X, part, gr, w, dir);
+        }
+#pragma unroll
+        for (int z = 0; z < ZH; ++z) gr[z] *= ih;
+      } else {
+        grad_z<Vr>(X, d, gr, w, ih);
+      }
+      // G_dir on the x, y and z lines through the node (offsets -6 .. 6)
+      if (X.active) {
+#pragma unroll
+        for (int z = 0; z < ZH; ++z) {
+          const int ox = X.cx - m, oy = X.cy - m, oz = z - m;
+          if (oy == 0 && oz == 0 && ox >= -SQ_FDM && ox <= SQ_FDM) S.kl[0][dir][ox + SQ_FDM] = gr[z];
+          if (ox == 0 && oz == 0 && oy >= -SQ_FDM && oy <= SQ_FDM) S.kl[1][dir][oy + SQ_FDM] = gr[z];
+          if (ox == 0 && oy == 0 && oz >= -SQ_FDM && oz <= SQ_FDM) S.kl[2][dir][oz + SQ_FDM] = gr[z];
+        }
+      }
+      if (dir == 0) near_sums<Vr, 0>(S, X, C, gr);
+      else if (dir == 1) near_sums<Vr, 1>(S, X, C, gr);
+      else near_sums<Vr, 2>(S, X, C, gr);
+    }
+    __syncthreads();
+    double* rec = P.rec + g * SQ_REC;
+    if (threadIdx.x == 0) {
+      // K_ab = 2 (grad_a G_b)(node), (grad_a G_b) = (1/h) sum_k w_k
+      // (G_b(+k e_a) - G_b(-k e_a)); points outside the cube hold zero
+      for (int a = 0; a < 3; ++a)
+        for (int bb = 0; bb < 3; ++bb) {
+          double acc = 0.0;
+          for (int k = 1; k <= SQ_FDM; ++k) acc += w[k] * (S.kl[a][bb][SQ_FDM + k] - S.kl[a][bb][SQ_FDM - k]);
+          rec[2 + 3 * a + bb] = 2.0 * acc * ih;
+        }
+      double N[9], enl = 0.0;
+      for (int t = 0; t < 9; ++t) N[t] = 0.0;
+      const int nnear = S.nnear;
+      for (int n = 0; n < nnear; ++n) {
+        const int i = S.near_img[n];
+        const double f = -2.0 * S.gdv[i] * S.near_chi[n];
+        double ns[10];
+        for (int t = 0; t < 10; ++t) ns[t] = fx_load(S.nsum[n][t]);
+        enl -= f * ns[0];   // 2 gamma dV chi_I(x_q) chi_I^T d_q
+        for (int a = 0; a < 3; ++a)
+          for (int bb = 0; bb < 3; ++bb) N[3 * a + bb] += f * ((a == bb ? ns[0] : 0.0) + 2.0 * ns[1 + 3 * a + bb]);
+      }
+      for (int t = 0; t < 9; ++t) rec[11 + t] = N[t];
+      rec[20] = enl;
+    }
+    node_epilogue<Vr>(X, P.err);
+  });
 }
 
 // ---------------------------------------------------------------------------
 // Capacity census (set-up time): per node the number of atom images reaching
 // its cube, the largest number crossing one z-column, and the number whose
-// projector is nonzero at the node.  Maxima per cell go to stats[4 * cell].
+// projector is nonzero at the node.  Maxima per cell go to
+// stats[SQ_CENSUS * cell + 0..2].
 // ---------------------------------------------------------------------------
 template <int NC>
 __global__ void __launch_bounds__(sq_threads(NC)) k_census(PlanDev P, const long long* items,
@@ -1214,9 +1367,9 @@ __global__ void __launch_bounds__(sq_threads(NC)) k_census(PlanDev P, const long
   }
   __syncthreads();
   if (tid == 0) {
-    atomicMax(&stats[4 * ci + 0], found);
-    atomicMax(&stats[4 * ci + 1], colmax);
-    atomicMax(&stats[4 * ci + 2], nnear);
+    atomicMax(&stats[SQ_CENSUS * ci + 0], found);
+    atomicMax(&stats[SQ_CENSUS * ci + 1], colmax);
+    atomicMax(&stats[SQ_CENSUS * ci + 2], nnear);
     atomicAdd(reinterpret_cast<unsigned long long*>(pair_total) + ci, npairs);
   }
 }
@@ -1231,85 +1384,97 @@ __global__ void __launch_bounds__(sq_threads(NC)) k_census(PlanDev P, const long
 namespace {
 constexpr int SQN = SQ_ONE_NC;
 
-enum Fam { FAM_LAN, FAM_MOM, FAM_STR, FAM_GRAM };
+enum Fam { FAM_LAN, FAM_MOM, FAM_STR };
 
-template <class Vr, int F, bool FUSED>
-hipError_t launch_var(const PlanDev& P, const long long* items, const int* ic, long long n,
-                      hipStream_t s) {
-  const dim3 grid((unsigned)n), block(Vr::L::NT);
-  if constexpr (F == FAM_LAN)
-    hipLaunchKernelGGL((k_lanczos<Vr, FUSED>), grid, block, 0, s, P, items, ic);
-  else if constexpr (F == FAM_MOM)
-    hipLaunchKernelGGL((k_moments<Vr, FUSED>), grid, block, 0, s, P, items, ic);
-  else if constexpr (F == FAM_STR)
-    hipLaunchKernelGGL((k_stress<Vr, FUSED>), grid, block, 0, s, P, items, ic);
-  else
-    hipLaunchKernelGGL(k_gram<Vr>, grid, block, 0, s, P, items, ic);
+template <class Vr, int F, bool FUSED, bool PERSIST>
+auto kernel_of() {
+  if constexpr (F == FAM_LAN) return &k_lanczos<Vr, FUSED, PERSIST>;
+  else if constexpr (F == FAM_MOM) return &k_moments<Vr, FUSED, PERSIST>;
+  else return &k_stress<Vr, FUSED, PERSIST>;
+}
+
+// One workgroup per node; or, PERSIST, as many workgroups as the device
+// holds at once (occupancy of the kernel times the number of CUs), each
+// taking nodes from the work counter, cleared first by a fill kernel (also
+// inside a captured graph).
+template <class Vr, int F, bool FUSED, bool PERSIST>
+hipError_t launch_one(const RecLaunch& R, const PlanDev& P, const long long* items, const int* ic,
+                      long long n, hipStream_t s) {
+  auto kern = kernel_of<Vr, F, FUSED, PERSIST>();
+  unsigned grid = (unsigned)n;
+  if constexpr (PERSIST) {
+    static int per_cu = 0;   // occupancy of this kernel (a property of the code object)
+    if (per_cu <= 0) {
+      int v = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, Vr::NT, 0) != hipSuccess || v < 1) v = 1;
+      per_cu = v;
+    }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const long long want = R.grid > 0 ? (long long)R.grid : (long long)per_cu * cus;
+    grid = (unsigned)(want < n ? want : n);
+    e = sq_launch_fill_u32(R.counter, 0u, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(Vr::NT), 0, s, P, items, ic, n, R.counter);
   return hipGetLastError();
 }
 
-// Nodes without a stored Gram matrix (rare: dense projector overlap) all use
-// the widest slot capacity, so only one two-sweep variant per precision is
-// compiled.
-template <int F, bool FUSED>
-hipError_t launch_fp64(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
-                       hipStream_t s) {
-  if constexpr (!FUSED) {
-    if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
-  } else {
-    if (kc <= 14) return launch_var<Var<double, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
-    if (kc <= 16) return launch_var<Var<double, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
-    if (kc <= 32) return launch_var<Var<double, SQN, 32, false>, F, FUSED>(P, items, ic, n, s);
-    if (kc <= 48) return launch_var<Var<double, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+template <class Vr, int F, bool FUSED, bool WITH_PERSIST>
+hipError_t launch_var(const RecLaunch& R, const PlanDev& P, const long long* items, const int* ic,
+                      long long n, hipStream_t s) {
+  if constexpr (WITH_PERSIST) {
+    if (R.counter) return launch_one<Vr, F, FUSED, true>(R, P, items, ic, n, s);
   }
-  return hipErrorInvalidValue;
+  return launch_one<Vr, F, FUSED, false>(R, P, items, ic, n, s);
 }
 
-template <int F, bool FUSED>
-hipError_t launch_fp32(int kc, const PlanDev& P, const long long* items, const int* ic, long long n,
-                       hipStream_t s) {
-  if constexpr (!FUSED) {
-    if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
-  } else {
-    if (kc <= 14) return launch_var<Var<float, SQN, 14, true>, F, FUSED>(P, items, ic, n, s);
-    if (kc <= 16) return launch_var<Var<float, SQN, 16, true>, F, FUSED>(P, items, ic, n, s);
-    if (kc <= 32) return launch_var<Var<float, SQN, 32, true>, F, FUSED>(P, items, ic, n, s);
-    if (kc <= 48) return launch_var<Var<float, SQN, 48, false>, F, FUSED>(P, items, ic, n, s);
+// The compiled variants per precision: sq_kc_pick gives the slot capacity
+// (16 with the plane weights in registers, or 48); nodes without a stored
+// Gram matrix (rare: dense projector overlap) all use the 48-slot two-sweep
+// form.  The persistent form is compiled for the 16-slot single-sweep
+// variant; the others run one workgroup per node.
+template <typename T, int F>
+hipError_t launch_t(const RecLaunch& R, const PlanDev& P, const long long* items, const int* ic,
+                    long long n, hipStream_t s) {
+  const int kc = sq_kc_pick(R.fused, R.kc);
+  if (!R.fused) {
+    if (kc == 48) return launch_var<Var<T, SQN, 48, false>, F, false, false>(R, P, items, ic, n, s);
+    return hipErrorInvalidValue;
   }
+  if (kc == 16) return launch_var<Var<T, SQN, 16, true>, F, true, true>(R, P, items, ic, n, s);
+  if (kc == 48) return launch_var<Var<T, SQN, 48, false>, F, true, false>(R, P, items, ic, n, s);
   return hipErrorInvalidValue;
-}
-
-template <int F>
-hipError_t launch_prec(bool fp64, bool fused, int kc, const PlanDev& P, const long long* items,
-                       const int* ic, long long n, hipStream_t s) {
-  if (fp64)
-    return fused ? launch_fp64<F, true>(kc, P, items, ic, n, s) : launch_fp64<F, false>(kc, P, items, ic, n, s);
-  return fused ? launch_fp32<F, true>(kc, P, items, ic, n, s) : launch_fp32<F, false>(kc, P, items, ic, n, s);
 }
 }  // namespace
 
-hipError_t SQ_CAT(sq_launch_lanczos_, SQ_ONE_NC)(int kc, bool fused, const PlanDev& P,
+hipError_t SQ_CAT(sq_launch_lanczos_, SQ_ONE_NC)(const RecLaunch& R, const PlanDev& P,
                                                 const long long* items, const int* ic, long long n,
                                                 hipStream_t s) {
-  return fused ? launch_fp64<FAM_LAN, true>(kc, P, items, ic, n, s)
-               : launch_fp64<FAM_LAN, false>(kc, P, items, ic, n, s);
+  return launch_t<double, FAM_LAN>(R, P, items, ic, n, s);
 }
 
-hipError_t SQ_CAT(sq_launch_moments_, SQ_ONE_NC)(bool fp64, int kc, bool fused, const PlanDev& P,
+hipError_t SQ_CAT(sq_launch_moments_, SQ_ONE_NC)(const RecLaunch& R, bool fp64, const PlanDev& P,
                                                 const long long* items, const int* ic, long long n,
                                                 hipStream_t s) {
-  return launch_prec<FAM_MOM>(fp64, fused, kc, P, items, ic, n, s);
+  return fp64 ? launch_t<double, FAM_MOM>(R, P, items, ic, n, s) : launch_t<float, FAM_MOM>(R, P, items, ic, n, s);
 }
 
-hipError_t SQ_CAT(sq_launch_stress_, SQ_ONE_NC)(bool fp64, int kc, bool fused, const PlanDev& P,
+hipError_t SQ_CAT(sq_launch_stress_, SQ_ONE_NC)(const RecLaunch& R, bool fp64, const PlanDev& P,
                                                const long long* items, const int* ic, long long n,
                                                hipStream_t s) {
-  return launch_prec<FAM_STR>(fp64, fused, kc, P, items, ic, n, s);
+  return fp64 ? launch_t<double, FAM_STR>(R, P, items, ic, n, s) : launch_t<float, FAM_STR>(R, P, items, ic, n, s);
 }
 
-hipError_t SQ_CAT(sq_launch_gram_, SQ_ONE_NC)(int kc, const PlanDev& P, const long long* items,
+// The Gram build always runs the widest FP64 variant (the entries do not
+// depend on the variant that reads them).
+hipError_t SQ_CAT(sq_launch_gram_, SQ_ONE_NC)(const PlanDev& P, const long long* items,
                                              const int* ic, long long n, hipStream_t s) {
-  return launch_fp64<FAM_GRAM, true>(kc, P, items, ic, n, s);
+  using Vr = Var<double, SQN, 48, false>;
+  hipLaunchKernelGGL(k_gram<Vr>, dim3((unsigned)n), dim3(Vr::NT), 0, s, P, items, ic);
+  return hipGetLastError();
 }
 
 hipError_t SQ_CAT(sq_launch_census_, SQ_ONE_NC)(const PlanDev& P, const long long* items,

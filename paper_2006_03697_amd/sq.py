@@ -29,7 +29,7 @@ SPECIES_KEYS = ("v_amp", "v_sigma", "v_rcut", "p_sigma", "p_rcut", "gamma", "z_v
 # checks both directions).
 EXPORTS = ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
            "sq_moments", "sq_lanczos", "sq_cell_info", "sq_phase_times", "sq_status_str", "sq_last_error",
-           "sq_destroy")
+           "sq_destroy", "sq_probe_lds")
 PHASES = ("lanczos", "bounds", "moments", "mu", "coeffs", "stress", "reduce")
 
 
@@ -60,7 +60,9 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class SqOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("hip_stream", ctypes.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
-                ("outputs_on_device", ctypes.c_int)]
+                ("outputs_on_device", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("cheb_quad_points", ctypes.c_int), ("persistent", ctypes.c_int)]
 
 
 _LIB = None
@@ -102,6 +104,8 @@ def load():
     L.sq_last_error.restype = ctypes.c_char_p
     L.sq_destroy.argtypes = [ctypes.c_void_p]
     L.sq_destroy.restype = None
+    L.sq_probe_lds.argtypes = [ctypes.c_int, ctypes.c_void_p, dp, dp]
+    L.sq_probe_lds.restype = ctypes.c_int
     for name in ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
                  "sq_moments", "sq_lanczos", "sq_cell_info", "sq_phase_times"):
         getattr(L, name).restype = ctypes.c_int
@@ -172,7 +176,9 @@ class Plan:
     """One sq_plan over a list of cells (same-name methods as the C ABI)."""
 
     def __init__(self, cells: Sequence[dict], precision: str = "fp64", stream=None,
-                 device: str = "cuda:0", use_torch_memory: bool = True):
+                 device: str = "cuda:0", use_torch_memory: bool = True, use_graph: bool = False,
+                 autotune: bool = False, tune_cache: Optional[str] = None, cheb_quad_points: int = 0,
+                 persistent: bool = False):
         import torch
         self.L = load()
         self.cells = list(cells)
@@ -195,6 +201,12 @@ class Plan:
             opt.dev_alloc = self._alloc.alloc_cb
             opt.dev_free = self._alloc.free_cb
         opt.outputs_on_device = 0
+        opt.use_graph = int(bool(use_graph))
+        opt.autotune = int(bool(autotune))
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        opt.tune_cache = self._tune_cache
+        opt.cheb_quad_points = int(cheb_quad_points)
+        opt.persistent = int(bool(persistent))
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = self.L.sq_setup(arr, len(self.cells), ctypes.byref(opt), ctypes.byref(handle))
@@ -203,7 +215,7 @@ class Plan:
         self.h = handle
         self.info = []
         for i in range(len(self.cells)):
-            inf = np.zeros(9, dtype=np.int64)
+            inf = np.zeros(10, dtype=np.int64)
             self._check(self.L.sq_cell_info(self.h, i, _i64(inf)), "sq_cell_info")
             self.info.append(inf)
 
@@ -285,7 +297,7 @@ class Plan:
     def lanczos(self, cell: int, nodes: Iterable[int]):
         """(steps, alpha [n, K], beta [n, K]) of the spectral-bound Lanczos."""
         nd = np.ascontiguousarray(np.asarray(list(nodes), dtype=np.int64))
-        K = int(self.cells[cell].get("lanczos_steps", 20))
+        K = int(self.info[cell][9])   # the step count in effect (0 means 20)
         out = np.zeros((nd.shape[0], 2 * K + 1))
         self._check(self.L.sq_lanczos(self.h, cell, _i64(nd), nd.shape[0], _dp(out)), "sq_lanczos")
         return out[:, 0].astype(int), out[:, 1:K + 1], out[:, K + 1:]
@@ -312,6 +324,22 @@ class Plan:
 
     def __exit__(self, *a):
         self.close()
+
+
+def probe_lds(bytes_per_lane: int = 8, stream=None):
+    """Measured conflict-free LDS read bandwidth (TB/s, bytes/clk/CU) of the
+    current device (include/sq_probe.h)."""
+    import torch
+    L = load()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    tb = ctypes.c_double()
+    bpc = ctypes.c_double()
+    st = L.sq_probe_lds(int(bytes_per_lane), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(tb),
+                        ctypes.byref(bpc))
+    if st != 0:
+        raise RuntimeError("sq_probe_lds failed with code %d" % st)
+    return tb.value, bpc.value
 
 
 def status_name(st: int) -> str:

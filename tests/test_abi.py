@@ -15,9 +15,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "sq.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return set(re.findall(r"\b(sq_[a-z_]+)\s*\(", text))
+    """Function names declared in every header under include/."""
+    names = set()
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not f.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(sq_[a-z_0-9]+)\s*\(", text))
+    return names
 
 
 def test_header_declarations_match_the_binding_and_the_library():
