@@ -128,6 +128,15 @@ typedef struct {
  *   persistent         0: one workgroup per node; 1: a persistent grid that
  *                      takes nodes from an atomic work counter (for groups
  *                      whose columns need at most 16 projector slots).
+ *   inject             0 in normal use.  Bits of sq_inject force the error
+ *                      paths for tests, from the host, with every kernel
+ *                      running to its normal end: SQ_INJECT_NARROW halves
+ *                      every node's spectral interval about its centre, so
+ *                      that the Chebyshev moments leave [-1, 1] and
+ *                      sq_density returns SQ_E_BOUNDS; SQ_INJECT_MU_CAP
+ *                      stops the Fermi-level search after 2 updates, so that
+ *                      sq_density returns SQ_E_NOCONV.  Other bits:
+ *                      SQ_E_ARG.
  * Node columns of a launch are ordered by decreasing Chebyshev degree
  * (longest first). */
 typedef struct {
@@ -142,7 +151,10 @@ typedef struct {
   const char* tune_cache;
   int cheb_quad_points;
   int persistent;
+  int inject;
 } sq_options;
+
+typedef enum { SQ_INJECT_NARROW = 1, SQ_INJECT_MU_CAP = 2 } sq_inject;
 
 /* Validate the cells, build the per-cell tables (grid, atom images, local
  * potential, per-tile image lists, the Gram matrix of each node's projectors)

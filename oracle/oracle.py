@@ -428,7 +428,23 @@ def lda_parts(rho):
     return ex, vx, ec, vc
 
 
-def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
+def _in_chunks(fn, nodes, per_node, progress, what, chunk=4096):
+    """fn(nodes, *per_node) over consecutive chunks of the nodes, results
+    stacked (the nodes are independent; chunking only lets a long run report
+    its progress)."""
+    if progress is None or len(nodes) <= chunk:
+        return fn(nodes, *per_node)
+    outs = []
+    for a in range(0, len(nodes), chunk):
+        b = min(a + chunk, len(nodes))
+        outs.append(fn(nodes[a:b], *[x[a:b] for x in per_node]))
+        progress("%s %d/%d" % (what, b, len(nodes)))
+    if isinstance(outs[0], tuple):
+        return tuple(np.concatenate([o[k] for o in outs]) for k in range(len(outs[0])))
+    return np.concatenate(outs)
+
+
+def run(cell: dict, nodes=None, mu=None, with_stress=True, progress=None) -> Result:
     """Full SQ evaluation of one cell.
 
     nodes=None: every node; mu from the electron count unless the cell's
@@ -441,12 +457,15 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
     dV rho_q (eps_xc - v_xc).  With the
     stress: sigma = (sum K + sum N) / |Omega| and the pressures
       P_direct = -(-2 E_band + 2 sum_q dV V_q rho_q + 2 E_nl + tr N) / (3 |Omega|)
-      P_trace  = -tr(K + N) / (3 |Omega|)."""
+      P_trace  = -tr(K + N) / (3 |Omega|).
+
+    progress: optional callable given a short message after each chunk of
+    nodes of the long stages."""
     oc = OracleCell(cell)
     all_nodes = nodes is None
     nodes = oc.nodes_all() if all_nodes else np.ascontiguousarray(nodes, dtype=np.int64)
-    lo, hi, chi, zeta = oc.bounds(nodes)
-    mom = oc.moments(nodes, chi, zeta)
+    lo, hi, chi, zeta = _in_chunks(oc.bounds, nodes, [], progress, "bounds")
+    mom = _in_chunks(oc.moments, nodes, [chi, zeta], progress, "moments")
     it = 0
     if mu is None:
         if cell.get("mu_mode", "solve") == "fixed":
@@ -480,7 +499,7 @@ def run(cell: dict, nodes=None, mu=None, with_stress=True) -> Result:
     rec[:, 22] = xc_e
     rec[:, 23] = xc_s
     if with_stress:
-        st = oc.stress_records(nodes, chi, zeta, c)
+        st = _in_chunks(oc.stress_records, nodes, [chi, zeta, c], progress, "stress")
         rec[:, 2:20] = st[:, 0:18]
         res["e_nl_node"] = st[:, 18].copy()
         parts = np.array([math.fsum(rec[:, 2 + k]) for k in range(18)])

@@ -796,6 +796,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   if (opt->cheb_quad_points != 0 &&
       (opt->cheb_quad_points < 4 || (opt->cheb_quad_points & (opt->cheb_quad_points - 1)) != 0))
     return fail(nullptr, SQ_E_ARG, "cheb_quad_points must be 0 or a power of two");
+  if (opt->inject & ~(SQ_INJECT_NARROW | SQ_INJECT_MU_CAP)) return fail(nullptr, SQ_E_ARG, "unknown inject bits");
   sq_plan p = new sq_plan_s();
   p->opt = *opt;
   p->stream = (hipStream_t)opt->hip_stream;
@@ -826,6 +827,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   const long long N = p->Ntot;
   PlanDev& P = p->P;
   P.mstride = npl_max + 2;
+  P.inject = opt->inject;
   auto A = [&](size_t bytes) { return dalloc(p, bytes); };
   P.lan = (double*)A(sizeof(double) * 2 * SQ_KL_MAX * N);
   P.lan_steps = (int*)A(sizeof(int) * N);

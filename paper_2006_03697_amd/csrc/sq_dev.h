@@ -71,6 +71,7 @@ struct PlanDev {
   unsigned* gidx;         // [Ntot][SQ_GRAM_MAX]
   int* gn;                // [Ntot]
   int mstride;
+  int inject;             // sq_options.inject (error-path tests)
 };
 
 // mus layout: SQ_MU_STRIDE doubles per cell

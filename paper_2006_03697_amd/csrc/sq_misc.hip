@@ -4,6 +4,7 @@
 // Clenshaw-Curtis coefficients, density and band energy per node, the
 // reductions and the local potential; and the dispatch of the recurrence
 // kernels over cube widths.
+#include "sq.h"
 #include "sq_devfn.h"
 
 namespace {
@@ -90,6 +91,11 @@ __global__ void k_bounds(PlanDev P, const long long* items, const int* item_cell
     const double smax = sqrt(fabs(last_component_sq(a, b, n, tmax)));
     lo = tmin - b[n - 1] * smin;
     hi = tmax + b[n - 1] * smax;
+  }
+  if (P.inject & SQ_INJECT_NARROW) {   // error-path tests: half the interval
+    const double c = 0.5 * (hi + lo), r = 0.25 * (hi - lo);
+    lo = c - r;
+    hi = c + r;
   }
   double* bd = P.bnd + 4 * g;
   bd[0] = lo;
@@ -409,7 +415,8 @@ __global__ void __launch_bounds__(256) k_mu_step(PlanDev P, const int* cells) {
     // a bracket collapsed to rounding level is a root to machine precision;
     // the update cap without that is a search that did not converge
     const bool collapsed = !(hi - lo > 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)));
-    if (collapsed || m[MU_IT] >= 200.0) {
+    const double cap = (P.inject & SQ_INJECT_MU_CAP) ? 2.0 : 200.0;
+    if (collapsed || m[MU_IT] >= cap) {
       m[MU_VAL] = mid;
       m[MU_DONE] = collapsed ? 1.0 : 3.0;
       m[MU_LO] = lo;

@@ -27,47 +27,71 @@ namespace {
 // ---------------------------------------------------------------------------
 // Cube layout in LDS and the thread <-> z-column map
 //
-// Padded layout: rows of RS >= NC + 6 elements (the tail zero) and planes of
-// NC + 6 rows (the last 6 zero), after 6 zero rows and 6 zeros, so every x/y
-// neighbour outside the cube reads a zero and needs no predicate; the zero
+// The mirror holds G consecutive planes of a column in one element (FP64:
+// two planes, 16 bytes; FP32: two planes, 8 bytes), so every x/y neighbour
+// read of the stencil serves G planes: FP64 reads are ds_read_b128, which
+// run at about 1.85x the bytes per clock of 8-byte reads on gfx950.  (Four
+// FP32 planes per 16-byte element would halve the FP32 reads again, but the
+// register tuples of the 16-byte loads then push the FP32 kernels into
+// kilobytes of spills.)
 //
-// LDS has 32 banks of 4 bytes: a 32-bit access by 32 lanes, or a 64-bit
-// access by 16 lanes, is conflict-free when the element addresses are
-// distinct modulo 32 (resp. 16).  With the padded row stride consecutive
+// Padded layout: rows of RS >= NC + 6 elements (the tail zero) and plane
+// groups of NC + 6 rows (the last 6 zero), after 6 zero rows and 6 zeros,
+// so every x/y neighbour outside the cube reads a zero and needs no
+// predicate; the zero rows and columns are shared by consecutive rows and
+// plane groups.
+//
+// LDS has 64 banks of 4 bytes: M = 256 / E lanes reading E bytes each
+// (E = 16: M = 16; E = 8: M = 32) are conflict-free when their element
+// indices are distinct modulo M.  With the padded row stride consecutive
 // rows alias, so lanes are mapped to columns by address residue instead of
-// row-major: lane 32 g + r owns the g-th column (in row-major order) whose
-// row offset cy * RS + cx is congruent to r modulo 32.  Every access of a
-// wave is then a constant shift of these offsets, hence conflict-free.  RS
-// is the smallest stride for which no residue class has more columns than
-// the block has 32-lane groups.
+// row-major: lane M g + r owns the g-th column (in row-major order) whose
+// row offset cy * RS + cx is congruent to r modulo M.  Every access of an
+// M-lane group is then a constant shift of these offsets, hence
+// conflict-free.  RS is the smallest stride for which no residue class has
+// more columns than the block has M-lane groups.
 // ---------------------------------------------------------------------------
-constexpr int sq_residue_max(int nc, int rs) {
+constexpr int sq_residue_max(int nc, int rs, int mod) {
   int cnt[32] = {};
   int mx = 0;
   for (int cy = 0; cy < nc; ++cy)
     for (int cx = 0; cx < nc; ++cx) {
-      const int r = (cy * rs + cx) & 31;
+      const int r = (cy * rs + cx) & (mod - 1);
       if (++cnt[r] > mx) mx = cnt[r];
     }
   return mx;
 }
 
-constexpr int sq_pick_rs(int nc) {
-  for (int rs = nc + SQ_FDM; rs <= nc + SQ_FDM + 16; ++rs)
-    if (sq_residue_max(nc, rs) * 32 <= sq_threads(nc)) return rs;
+constexpr int sq_pick_rs(int nc, int mod) {
+  for (int rs = nc + SQ_FDM; rs <= nc + SQ_FDM + 32; ++rs)
+    if (sq_residue_max(nc, rs, mod) * mod <= sq_threads(nc)) return rs;
   return 0;
 }
 
-template <int NC, bool PAD>
+// vectors of two values: the mirror element of both precisions, and the
+// packed (rr(0), cq) pair of an image
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+
+template <int NC, int G, int M, bool PAD>
 struct Lay {
   static constexpr int NTC = sq_threads(NC);   // threads (one per column)
   static constexpr int MH = NC / 2;
-  static constexpr int RS = PAD ? sq_pick_rs(NC) : NC;              // row stride
-  static constexpr int PL = PAD ? (NC + SQ_FDM) * RS : NC * NC;     // plane stride
+  static constexpr int NZG = (NC + G - 1) / G;                      // plane groups
+  static constexpr int RS = PAD ? sq_pick_rs(NC, M) : NC;           // row stride
+  static constexpr int PL = PAD ? (NC + SQ_FDM) * RS : NC * NC;     // plane-group stride
   static constexpr int X0 = PAD ? SQ_FDM * RS + SQ_FDM : 0;         // offset of (0, 0, 0)
-  static constexpr int SIZE = X0 + NC * PL;
+  static constexpr int SIZE = X0 + NZG * PL;                        // elements
   static_assert(!PAD || RS > 0, "no conflict-free row stride");
-  __device__ static constexpr int at(int x, int y, int z) { return X0 + z * PL + y * RS + x; }
+  __device__ static constexpr int at(int x, int y, int zg) { return X0 + zg * PL + y * RS + x; }
 
   // Column of local thread t (see above); inactive threads own no column.
   __device__ static void column(int t, int& cx, int& cy, bool& active) {
@@ -75,11 +99,11 @@ struct Lay {
     cy = 0;
     active = false;
     if constexpr (PAD) {
-      const int r = t & 31, g = t >> 5;
+      const int r = t & (M - 1), g = t / M;
       int seen = 0;
       for (int y = 0; y < NC; ++y) {
-        const int x = (r - y * RS) & 31;   // the one column of row y with residue r
-        if (x < NC) {
+        // the columns of row y with residue r (x0, x0 + M, ...)
+        for (int x = (r - y * RS) & (M - 1); x < NC; x += M) {
           if (seen == g) {
             cx = x;
             cy = y;
@@ -118,41 +142,50 @@ struct Var {
   static constexpr int GPT = (GCAP + NT - 1) / NT;   // Gram entries per thread (registers)
   static_assert(NIMG <= (1 << IBITS) && NIMG <= 65536, "image index width");
   static_assert(NT <= 1024, "workgroup size");
-  static constexpr size_t OTHER = 8 * (size_t)NIMG * 9 + 8 * 2 * (size_t)NIMG +
+  static constexpr size_t OTHER = 8 * (size_t)NIMG * 9 + 8 * 4 * (size_t)NIMG +
                                   16 * (size_t)NIMG + 16 * (size_t)NEAR * 10 + (size_t)NEAR * 12 +
-                                  2 * 2 * 16 * 8 + 8 * 9 * (2 * SQ_FDM + 1) + 256;
+                                  2 * 2 * 16 * 8 + 256;   // the stress line buffer shares pint's space
   // scratch of the Gram build in the cube buffer: pair bitmap [NIMG][NWD],
   // row starts [NIMG + 1], slot words [KC][NT], two-word sums [GCAP][2]
   static constexpr int NWD = (NIMG + 31) / 32;
   static constexpr size_t GSCR = 4 * ((size_t)NIMG * NWD + NIMG + 1 + (size_t)KC * NT) + 8 +
                                  16 * (size_t)GCAP;
+  using V = typename Vec2<T_>::type;   // mirror element: two planes
+  static constexpr int G = 2;
+  static constexpr int M = 256 / (int)sizeof(V);   // lanes per conflict-free group
 #ifdef SQ_NO_PAD
   static constexpr bool PAD = false;
 #else
-  static constexpr bool PAD = sizeof(T_) * (size_t)Lay<NC_, true>::SIZE + OTHER <= 163840;
+  static constexpr bool PAD = sizeof(V) * (size_t)Lay<NC_, G, M, true>::SIZE + OTHER <= 163840;
 #endif
-  using L = Lay<NC_, PAD>;
+  using L = Lay<NC_, G, M, PAD>;
   static constexpr int MH = NC_ / 2;
-  // elements of the cube buffer: the cube, or the Gram scratch
-  static constexpr size_t TLN = (GSCR + sizeof(T_) - 1) / sizeof(T_) > (size_t)L::SIZE
-                                    ? (GSCR + sizeof(T_) - 1) / sizeof(T_)
-                                    : (size_t)L::SIZE;
+  // elements of the cube buffer: the mirror, or the Gram scratch
+  static constexpr size_t GEL = (GSCR + sizeof(V) - 1) / sizeof(V);
+  static constexpr size_t TLN = GEL > (size_t)L::SIZE ? GEL : (size_t)L::SIZE;
 };
 
 template <class Vr>
 struct Smem {
   using T = typename Vr::T;
   static constexpr int NI = Vr::NIMG;
-  T tl[Vr::TLN];
+  typename Vr::V tl[Vr::TLN];          // the mirror (G planes per element), or scratch
   double ix[NI], iy[NI], iz[NI];      // image positions (unwrapped), sorted by z
   double rp2[NI], i2s[NI], gdv[NI];   // r_p^2, 1 / (2 sigma_p^2), gamma dV
   // z factor of each image on the cube planes: e(z) = exp(-u_z^2 i2s) with
-  // u_z = u_0 + z h, generated as e(z + 1) = e(z) rr(z), rr(z + 1) = rr(z) cq
-  double e0[NI], r0[NI], cq[NI];
+  // u_z = u_0 + z h, generated as e(z + 1) = e(z) rr(z), rr(z + 1) = rr(z) cq;
+  // rq = (rr(0), cq) (one 16-byte read per slot and step)
+  double e0[NI];
+  typename Vec2<double>::type rq[NI];
   double pf[2][NI];                   // projections <chi_I, v>, double-buffered over steps
-  unsigned long long pint[NI][2];     // projection sums being formed (two-word integers)
+  double gpf[2][NI];                  // gamma dV <chi_I, v>
+  union {
+    unsigned long long pint[NI][2];   // projection sums being formed (two-word integers)
+    // stress pass, after the last step: G_b = grad_b d on the line through
+    // the node along a
+    double kl[3][3][2 * SQ_FDM + 1];
+  };
   unsigned long long nsum[Vr::NEAR][10][2];   // stress pass: sums over near images' supports
-  double kl[3][3][2 * SQ_FDM + 1];    // stress pass: G_b = grad_b d on the line through the node along a
   double red[2][2 * 16];              // block sums, double-buffered over steps
   double near_chi[Vr::NEAR];
   int near_img[Vr::NEAR];
@@ -170,7 +203,7 @@ struct Ctx {
   long long q0, q1, q2;
   int nslot;    // slots of this column
   int nsw;      // largest slot count in the wave (wave-uniform)
-  int bown;     // LDS element offset of the column's plane 0
+  int bown;     // LDS element of the column's plane group 0
   // slot s: bit 31 - z set for the planes z of the chord of the image's
   // spherical support on this column; the image index in the low bits
   unsigned sid[Vr::KC];
@@ -334,14 +367,15 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
       cq = exp(-2.0 * h * h * is);
     }
     S.e0[i] = e0;
-    S.r0[i] = r0;
-    S.cq[i] = cq;
+    S.rq[i] = typename Vec2<double>::type{r0, cq};
     S.pf[0][i] = 0.0;
     S.pf[1][i] = 0.0;
+    S.gpf[0][i] = 0.0;
+    S.gpf[1][i] = 0.0;
     S.pint[i][0] = 0ull;
     S.pint[i][1] = 0ull;
   }
-  for (int i = tid; i < (int)Vr::TLN; i += NT) S.tl[i] = (T)0;
+  for (int i = tid; i < (int)Vr::TLN; i += NT) S.tl[i] = typename Vr::V{};
   if (tid == 0) S.nnear = 0;
   __syncthreads();
 
@@ -426,7 +460,9 @@ __device__ __forceinline__ double chord_weight<double>(bool on, double a) {
 // on the planes of the chord, zero elsewhere.  f(z, on, w) is called for
 // every plane.
 template <int ZH, class F>
-__device__ __forceinline__ void slot_sweep(unsigned mk, double a, double rr, double cq, F f) {
+__device__ __forceinline__ void slot_sweep(unsigned mk, double a, typename Vec2<double>::type rq, F f) {
+  double rr = rq.x;
+  const double cq = rq.y;
 #pragma unroll
   for (int z = 0; z < ZH; ++z) {
     unsigned nm;
@@ -452,7 +488,7 @@ __device__ __forceinline__ void project(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& 
       const unsigned mk = X.sid[s];
       const int i = (int)(mk & IMASK);
       T part = (T)0;
-      slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+      slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
                          [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
       // a slot past the thread's count has sid 0 and weight zero: it adds 0 to image 0
       fx_add(S.pint[i], (double)part, X.bad);
@@ -469,7 +505,9 @@ __device__ __forceinline__ void finish_proj(Smem<Vr>& S, int par, double alpha =
   for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::NT) {
     double v = fx_load(S.pint[i]);
     if (alpha != 0.0) v -= alpha * S.pf[par][i];
-    S.pf[par ^ 1][i] = v * ib;
+    v *= ib;
+    S.pf[par ^ 1][i] = v;
+    S.gpf[par ^ 1][i] = S.gdv[i] * v;
     S.pint[i][0] = 0ull;
     S.pint[i][1] = 0ull;
   }
@@ -525,35 +563,55 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
           const double gval = X.gvp[kk];
           const unsigned ij = in ? X.gip[kk] : 0u;
           const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
-          fx_add(S.pint[i], in ? gval * (sc * S.gdv[j] * S.pf[par][j]) : 0.0, X.bad);
+          fx_add(S.pint[i], in ? gval * (sc * S.gpf[par][j]) : 0.0, X.bad);
         }
       }
     }
   }
-  // (2) stencil + diagonal on the own planes (x/y neighbours from LDS, z
-  // neighbours from registers or, across the plane split, from LDS)
+  // (2) stencil + diagonal on the own planes (x/y neighbours from LDS, G
+  // planes per read; z neighbours from registers)
   if (X.active) {
+    using V = typename Vr::V;
+    constexpr int G = Vr::G;
     const T tsc = (T)sc;
 #pragma unroll
-    for (int z = 0; z < ZH; ++z) {
-      T acc = X.vd[z] * cur[z];
-      const T* pc = S.tl + X.bown + z * L::PL;
+    for (int zg = 0; zg < L::NZG; ++zg) {
+      T acc[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int z = zg * G + u;
+        acc[u] = z < ZH ? X.vd[z] * cur[z] : (T)0;
+      }
+      const V* pc = S.tl + X.bown + zg * L::PL;
 #pragma unroll
       for (int k = 1; k <= SQ_FDM; ++k) {
-        T s = (T)0;
-        if (z + k < ZH) s += cur[z + k];
-        if (z - k >= 0) s += cur[z - k];
+        V h;
         if constexpr (L::RS > Vr::NC) {
-          s += (pc[k] + pc[-k]) + (pc[k * L::RS] + pc[-k * L::RS]);
+          h = (pc[k] + pc[-k]) + (pc[k * L::RS] + pc[-k * L::RS]);
         } else {
-          if (X.cx + k < Vr::NC) s += pc[k];
-          if (X.cx - k >= 0) s += pc[-k];
-          if (X.cy + k < Vr::NC) s += pc[k * L::RS];
-          if (X.cy - k >= 0) s += pc[-k * L::RS];
+          h = V{};
+          if (X.cx + k < Vr::NC) h += pc[k];
+          if (X.cx - k >= 0) h += pc[-k];
+          if (X.cy + k < Vr::NC) h += pc[k * L::RS];
+          if (X.cy - k >= 0) h += pc[-k * L::RS];
         }
-        acc += ck[k] * s;
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int z = zg * G + u;
+          if (z < ZH) {
+            T s = (T)0;
+            if (z + k < ZH) s += cur[z + k];
+            if (z - k >= 0) s += cur[z - k];
+            s += h[u];
+            acc[u] += ck[k] * s;
+          }
+        }
       }
-      io[z] = tsc * acc - pm * io[z];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int z = zg * G + u;
+        if (z < ZH) io[z] = tsc * acc[u] - pm * io[z];
+      }
     }
     // optional cw w_q (the unit vector at the node): part of the vector the
     // projector terms are added to, and of its projections
@@ -567,9 +625,9 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       if (s < nsw) {
         const unsigned mk = X.sid[s];
         const int i = (int)(mk & IMASK);
-        const T coef = (T)(sc * S.gdv[i] * S.pf[par][i]);
+        const T coef = (T)(sc * S.gpf[par][i]);
         T part = (T)0;
-        slot_sweep<ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+        slot_sweep<ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
                        [&](int z, bool on, double a) {
                          const T w = chord_weight<T>(on, a);
                          part += w * io[z];
@@ -585,8 +643,8 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
       if (s < nsw) {
         const unsigned mk = X.sid[s];
         const int i = (int)(mk & IMASK);
-        const double coef = s < X.nslot ? sc * S.gdv[i] * S.pf[par][i] : 0.0;
-        slot_sweep<ZH>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+        const double coef = s < X.nslot ? sc * S.gpf[par][i] : 0.0;
+        slot_sweep<ZH>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.rq[i],
                        [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
       }
     }
@@ -600,10 +658,16 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
 template <class Vr>
 __device__ __forceinline__ void mirror(Smem<Vr>& S, const Ctx<Vr>& X, const typename Vr::T (&v)[Vr::ZH]) {
   using L = typename Vr::L;
+  using V = typename Vr::V;
+  constexpr int G = Vr::G;
   if (X.active) {
 #pragma unroll
-    for (int z = 0; z < Vr::ZH; ++z)
-      S.tl[X.bown + z * L::PL] = v[z];
+    for (int zg = 0; zg < L::NZG; ++zg) {
+      V e;
+#pragma unroll
+      for (int u = 0; u < G; ++u) e[u] = zg * G + u < Vr::ZH ? v[zg * G + u] : (typename Vr::T)0;
+      S.tl[X.bown + zg * L::PL] = e;
+    }
   }
 }
 
@@ -781,8 +845,8 @@ __device__ void gram_build(Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C, unsi
         const double wj = exp(-sq_sum2(node_coord(X.q0 + X.cx - m, h, S.ix[j]),
                                        node_coord(X.q1 + X.cy - m, h, S.iy[j])) * S.i2s[j]) *
                           S.e0[j];
-        double ai = wi, ri = S.r0[i], aj = wj, rj = S.r0[j];
-        const double qi = S.cq[i], qj = S.cq[j];
+        double ai = wi, ri = S.rq[i].x, aj = wj, rj = S.rq[j].x;
+        const double qi = S.rq[i].y, qj = S.rq[j].y;
         long long shi = 0, slo = 0;
         unsigned mk = a & b & ~IMASK;
 #pragma unroll
@@ -1011,7 +1075,7 @@ __global__ void __launch_bounds__(Vr::NT) k_moments(PlanDev P, const long long* 
       // |rho^j| <= 1 when the bounds hold: 1e-6 slack for FP64 rounding, 1e-4
       // for FP32 vectors (their rounding reaches 1e-6 near |rho^j| = 1)
       constexpr double btol = sizeof(T) == 8 ? 1e-6 : 1e-4;
-      if (fabs(r1) > 1.0 + btol || (j2 <= npl && fabs(r2) > 1.0 + btol) || !(r1 == r1)) bad = true;
+      if (!(fabs(r1) <= 1.0 + btol) || (j2 <= npl && !(fabs(r2) <= 1.0 + btol))) bad = true;
       if (threadIdx.x == 0) {
         mom[j1] = r1;
         if (j2 <= npl) mom[j2] = r2;
@@ -1041,25 +1105,41 @@ __device__ __forceinline__ void grad_round(Smem<Vr>& S, Ctx<Vr>& X, const typena
                                            double (&g)[Vr::ZH], const double* w, int dir) {
   using T = typename Vr::T;
   using L = typename Vr::L;
+  using V = typename Vr::V;
+  constexpr int G = Vr::G;
   mirror<Vr>(S, X, part);
   __syncthreads();
   if (X.active) {
     const int st = dir == 0 ? 1 : L::RS;
     const int pos = dir == 0 ? X.cx : X.cy;
 #pragma unroll
-    for (int z = 0; z < Vr::ZH; ++z) {
-      const T* pc = S.tl + X.bown + z * L::PL;
-      double a = 0.0;
+    for (int zg = 0; zg < L::NZG; ++zg) {
+      const V* pc = S.tl + X.bown + zg * L::PL;
+      double a[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) a[u] = 0.0;
 #pragma unroll
       for (int k = 1; k <= SQ_FDM; ++k) {
         if constexpr (L::RS > Vr::NC) {
-          a += w[k] * ((double)pc[k * st] - (double)pc[-k * st]);
+          const V p = pc[k * st], q = pc[-k * st];
+#pragma unroll
+          for (int u = 0; u < G; ++u) a[u] += w[k] * ((double)p[u] - (double)q[u]);
         } else {
-          if (pos + k < Vr::NC) a += w[k] * (double)pc[k * st];
-          if (pos - k >= 0) a -= w[k] * (double)pc[-k * st];
+          if (pos + k < Vr::NC) {
+            const V p = pc[k * st];
+#pragma unroll
+            for (int u = 0; u < G; ++u) a[u] += w[k] * (double)p[u];
+          }
+          if (pos - k >= 0) {
+            const V q = pc[-k * st];
+#pragma unroll
+            for (int u = 0; u < G; ++u) a[u] -= w[k] * (double)q[u];
+          }
         }
       }
-      g[z] += a;
+#pragma unroll
+      for (int u = 0; u < G; ++u)
+        if (zg * G + u < Vr::ZH) g[zg * G + u] += a[u];
     }
   }
   __syncthreads();
@@ -1108,7 +1188,7 @@ __device__ __forceinline__ void near_sums(Smem<Vr>& S, Ctx<Vr>& X, const CellDev
       if (nidx >= 0) {
         const double rx = xc - S.ix[i], ry = yc - S.iy[i];
         double acc[3] = {0.0, 0.0, 0.0};
-        slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.r0[i], S.cq[i],
+        slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
                            [&](int z, bool on, double chiv) {
                              if (on) {
                                if constexpr (DIR < 0) {

@@ -21,6 +21,7 @@ SQ_OK, SQ_E_ARG, SQ_E_ALLOC, SQ_E_DEVICE, SQ_E_BOUNDS, SQ_E_NOCONV, SQ_E_STATE =
 SQ_FP64, SQ_MIXED, SQ_MIXED_STRESS = 0, 1, 2
 PRECISIONS = {"fp64": SQ_FP64, "mixed": SQ_MIXED, "mixed_stress": SQ_MIXED_STRESS}
 SQ_MU_SOLVE, SQ_MU_FIXED = 0, 1
+SQ_INJECT_NARROW, SQ_INJECT_MU_CAP = 1, 2
 REC = 24
 
 SPECIES_KEYS = ("v_amp", "v_sigma", "v_rcut", "p_sigma", "p_rcut", "gamma", "z_val")
@@ -62,7 +63,8 @@ class SqOptions(ctypes.Structure):
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
                 ("outputs_on_device", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
-                ("cheb_quad_points", ctypes.c_int), ("persistent", ctypes.c_int)]
+                ("cheb_quad_points", ctypes.c_int), ("persistent", ctypes.c_int),
+                ("inject", ctypes.c_int)]
 
 
 _LIB = None
@@ -178,7 +180,7 @@ class Plan:
     def __init__(self, cells: Sequence[dict], precision: str = "fp64", stream=None,
                  device: str = "cuda:0", use_torch_memory: bool = True, use_graph: bool = False,
                  autotune: bool = False, tune_cache: Optional[str] = None, cheb_quad_points: int = 0,
-                 persistent: bool = False):
+                 persistent: bool = False, inject: int = 0):
         import torch
         self.L = load()
         self.cells = list(cells)
@@ -207,6 +209,7 @@ class Plan:
         opt.tune_cache = self._tune_cache
         opt.cheb_quad_points = int(cheb_quad_points)
         opt.persistent = int(bool(persistent))
+        opt.inject = int(inject)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = self.L.sq_setup(arr, len(self.cells), ctypes.byref(opt), ctypes.byref(handle))
