@@ -185,6 +185,23 @@ sq_status sq_energy(sq_plan plan, int cell, double* e_band);
  * of K (3x3) then N (3x3), not divided by |Omega|.  Needs sq_density. */
 sq_status sq_stress(sq_plan plan, int cell, double* sigma_voigt, double* parts);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): sq_stress with the per-cell sums of its stress reduction
+ * formed in a static device array of the library instead of plan memory.
+ * Same arguments, outputs (bit for bit) and errors as sq_stress; it
+ * allocates no device memory (no hipMalloc, no allocator callback) and, on
+ * success, no host memory, and always runs the stress pass eagerly, never
+ * from a captured graph.  The array holds 1024 rows of 28 doubles (229 KB); each
+ * GPU the library runs on holds its own copy until the process ends, and
+ * its address is taken once per device at sq_setup.  SQ_E_ARG for a plan
+ * of more than 1024 cells.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (several host threads or streams) race.
+ * The plan's own stress sums are not written, so sq_pressure after it runs
+ * its own stress pass unless sq_stress has run since the last
+ * sq_density. */
+sq_status sq_stress_static(sq_plan plan, int cell, double* sigma_voigt, double* parts);
+
 /* Pressure, P = -(sigma_11 + sigma_22 + sigma_33)/3 of the kinetic + nonlocal
  * stress, one value per cell in each output (either may be NULL), in two
  * forms:

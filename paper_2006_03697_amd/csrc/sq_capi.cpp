@@ -96,6 +96,8 @@ struct sq_plan_s {
   Selection all;
   std::vector<Selection> per_cell;
   std::vector<int> density_done, stress_done;
+  double* static_sums = nullptr;     // this device's static scratch (sq_stress_static)
+  std::vector<double> host_sums;     // its host copy, sized at set-up
   long long Ntot = 0;
   std::vector<CellDev> host_cells;   // what was uploaded to d_cells
   std::map<std::string, Tile> tuned; // autotuned tiles by key
@@ -540,7 +542,7 @@ sq_status enqueue_density(sq_plan p, Selection* S, hipStream_t s) {
 
 // Density-matrix columns, their gradients, K and N per node, the nonlocal
 // energy per node, and the node sums of those columns.
-sq_status enqueue_stress(sq_plan p, Selection* S, hipStream_t s) {
+sq_status enqueue_stress(sq_plan p, Selection* S, hipStream_t s, double* sums = nullptr) {
   const bool fp64 = p->opt.precision == SQ_FP64;
   sq_status st = check_hip(p, sq_launch_fill_u32(p->P.err, 0u, 1, s), "clear");
   phase_begin(p, PH_STRESS, s);
@@ -550,8 +552,10 @@ sq_status enqueue_stress(sq_plan p, Selection* S, hipStream_t s) {
                      "stress");
   phase_end(p, PH_STRESS, s);
   phase_begin(p, PH_REDUCE, s);
+  PlanDev Pr = p->P;
+  if (sums) Pr.sums = sums;   // the reduction's target (default: the plan's sums)
   if (st == SQ_OK)
-    st = check_hip(p, sq_launch_reduce(p->P, S->d_cells, (int)S->cells.size(), 2, 19, s), "reduce");
+    st = check_hip(p, sq_launch_reduce(Pr, S->d_cells, (int)S->cells.size(), 2, 19, s), "reduce");
   phase_end(p, PH_REDUCE, s);
   return st;
 }
@@ -742,6 +746,27 @@ sq_status autotune(sq_plan p) {
   return st;
 }
 
+}  // namespace
+
+namespace {
+// sigma (Voigt) and the K, N node sums of the selected cells from the
+// reduced records (rows of SQ_REC + 4 per plan cell)
+sq_status stress_outputs(sq_plan p, const Selection* S, const double* sums, double* sigma_voigt,
+                         double* parts) {
+  sq_status st = SQ_OK;
+  for (size_t i = 0; i < S->cells.size(); ++i) {
+    const int ci = S->cells[i];
+    const double* pr = &sums[(SQ_REC + 4) * ci + 2];
+    const double vol = p->cells[ci].vol;
+    double sg[9];
+    for (int t = 0; t < 9; ++t) sg[t] = (pr[t] + pr[9 + t]) / vol;
+    double v6[6] = {sg[0], sg[4], sg[8], 0.5 * (sg[5] + sg[7]), 0.5 * (sg[2] + sg[6]),
+                    0.5 * (sg[1] + sg[3])};
+    if (sigma_voigt && st == SQ_OK) st = put_out(p, sigma_voigt + 6 * i, v6, sizeof(v6));
+    if (parts && st == SQ_OK) st = put_out(p, parts + 18 * i, pr, sizeof(double) * 18);
+  }
+  return st;
+}
 }  // namespace
 
 extern "C" {
@@ -987,6 +1012,16 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   }
   p->density_done.assign(n_cells, 0);
   p->stress_done.assign(n_cells, 0);
+  // the library's static scratch on this device (sq_stress_static)
+  if (n_cells <= SQ_STATIC_CELLS) {
+    st = check_hip(p, sq_static_scratch(&p->static_sums), "static scratch");
+    if (st != SQ_OK) {
+      g_setup_err = p->err;
+      sq_destroy(p);
+      return st;
+    }
+    p->host_sums.assign((size_t)(SQ_REC + 4) * n_cells, 0.0);
+  }
   *out = p;
   return SQ_OK;
 }
@@ -1157,18 +1192,35 @@ sq_status sq_stress(sq_plan p, int cell, double* sigma_voigt, double* parts) {
   std::vector<double> sums;
   st = stress_pass(p, S, sums);
   if (st != SQ_OK) return st;
-  for (size_t i = 0; i < S->cells.size(); ++i) {
-    const int ci = S->cells[i];
-    const double* pr = &sums[(SQ_REC + 4) * ci + 2];
-    const double vol = p->cells[ci].vol;
-    double sg[9];
-    for (int t = 0; t < 9; ++t) sg[t] = (pr[t] + pr[9 + t]) / vol;
-    double v6[6] = {sg[0], sg[4], sg[8], 0.5 * (sg[5] + sg[7]), 0.5 * (sg[2] + sg[6]),
-                    0.5 * (sg[1] + sg[3])};
-    if (sigma_voigt && st == SQ_OK) st = put_out(p, sigma_voigt + 6 * i, v6, sizeof(v6));
-    if (parts && st == SQ_OK) st = put_out(p, parts + 18 * i, pr, sizeof(double) * 18);
-  }
-  return st;
+  return stress_outputs(p, S, sums.data(), sigma_voigt, parts);
+}
+
+sq_status sq_stress_static(sq_plan p, int cell, double* sigma_voigt, double* parts) {
+  if (!p) return SQ_E_ARG;
+  if ((int)p->cells.size() > SQ_STATIC_CELLS)
+    return fail(p, SQ_E_ARG, "sq_stress_static: the plan has " + std::to_string(p->cells.size()) +
+                                 " cells; the static scratch holds " + std::to_string(SQ_STATIC_CELLS));
+  if (!p->static_sums) return fail(p, SQ_E_DEVICE, "sq_stress_static: no static scratch on this device");
+  Selection* S = nullptr;
+  sq_status st = select(p, cell, &S);
+  if (st != SQ_OK) return st;
+  for (int ci : S->cells)
+    if (!p->density_done[ci]) return fail(p, SQ_E_STATE, "sq_stress_static before sq_density");
+  // always eager: a captured stress graph reduces into the plan's own sums.
+  // The reduction writes every row it covers before it is read (nothing
+  // needs clearing); rows of other cells keep an earlier call's contents
+  // and are not read.
+  st = enqueue_stress(p, S, p->stream, p->static_sums);
+  if (st == SQ_OK) st = check_errors(p);
+  phase_collect(p);
+  if (st == SQ_OK)
+    st = check_hip(p, hipMemcpyAsync(p->host_sums.data(), p->static_sums, sizeof(double) * p->host_sums.size(),
+                                     hipMemcpyDeviceToHost, p->stream), "static sums");
+  if (st == SQ_OK) st = check_hip(p, hipStreamSynchronize(p->stream), "static sums");
+  if (st != SQ_OK) return st;
+  // the plan's stress bookkeeping is left as it was: sq_pressure reads the
+  // plan's own sums, which this call does not write
+  return stress_outputs(p, S, p->host_sums.data(), sigma_voigt, parts);
 }
 
 sq_status sq_pressure(sq_plan p, int cell, double* p_direct, double* p_trace) {

@@ -128,6 +128,14 @@ hipError_t sq_launch_stress(const RecLaunch& R, bool fp64, const PlanDev& P,
 hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, int* stats, long long* pairs, hipStream_t s);
 hipError_t sq_launch_fill_u32(unsigned* p, unsigned v, long long n, hipStream_t s);
+
+// Static device scratch of the library (sq_misc.hip): SQ_STATIC_CELLS rows of
+// SQ_REC + 4 doubles, one array per GPU for the life of the process, used by
+// the entry point that allocates nothing.  sq_static_scratch() returns the
+// current device's address of the array (looked up once per device).
+#define SQ_STATIC_CELLS 1024
+#define SQ_STATIC_DEVICES 64
+hipError_t sq_static_scratch(double** ptr);
 // slot capacity of the variant that serves a need of kc slots per column
 // (0: none)
 int sq_kc_variant(bool fused, int kc);

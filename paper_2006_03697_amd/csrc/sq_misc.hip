@@ -4,6 +4,8 @@
 // Clenshaw-Curtis coefficients, density and band energy per node, the
 // reductions and the local potential; and the dispatch of the recurrence
 // kernels over cube widths.
+#include <mutex>
+
 #include "sq.h"
 #include "sq_devfn.h"
 
@@ -600,4 +602,32 @@ hipError_t sq_launch_reduce(const PlanDev& P, const int* cells, int ncells, int 
                             hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(ncells), dim3(256), 0, s, P, cells, col0, ncol);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch: per-cell sums of the stress reduction for sq_stress_static
+// (SQ_STATIC_CELLS rows of SQ_REC + 4 doubles; each GPU the library runs on
+// holds its own copy until the process ends).  Host code never passes the
+// array's name to a kernel: that is a host-side stand-in, not the device
+// address.  The address comes from hipGetSymbolAddress, once per device with
+// that device current, and is kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[SQ_STATIC_CELLS * (SQ_REC + 4)];
+
+hipError_t sq_static_scratch(double** out) {
+  static std::mutex mu;
+  static double* ptr[SQ_STATIC_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SQ_STATIC_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }

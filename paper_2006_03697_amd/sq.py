@@ -28,7 +28,7 @@ SPECIES_KEYS = ("v_amp", "v_sigma", "v_rcut", "p_sigma", "p_rcut", "gamma", "z_v
 
 # Names declared in include/sq.h (kept in step with the header; a CPU test
 # checks both directions).
-EXPORTS = ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
+EXPORTS = ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_stress_static", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
            "sq_moments", "sq_lanczos", "sq_cell_info", "sq_phase_times", "sq_status_str", "sq_last_error",
            "sq_destroy", "sq_probe_lds")
 PHASES = ("lanczos", "bounds", "moments", "mu", "coeffs", "stress", "reduce")
@@ -92,6 +92,7 @@ def load():
     L.sq_density.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_energy.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     L.sq_stress.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
+    L.sq_stress_static.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_pressure.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_xc.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, dp]
     L.sq_nodes.argtypes = [ctypes.c_void_p, ctypes.c_int, i64p, ctypes.c_int64, dp]
@@ -108,7 +109,8 @@ def load():
     L.sq_destroy.restype = None
     L.sq_probe_lds.argtypes = [ctypes.c_int, ctypes.c_void_p, dp, dp]
     L.sq_probe_lds.restype = ctypes.c_int
-    for name in ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_pressure", "sq_xc", "sq_nodes", "sq_bounds",
+    for name in ("sq_setup", "sq_density", "sq_energy", "sq_stress", "sq_stress_static", "sq_pressure", "sq_xc",
+                 "sq_nodes", "sq_bounds",
                  "sq_moments", "sq_lanczos", "sq_cell_info", "sq_phase_times"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
@@ -259,6 +261,15 @@ class Plan:
         sig = np.zeros(6 * n)
         parts = np.zeros(18 * n)
         self._check(self.L.sq_stress(self.h, cell, _dp(sig), _dp(parts)), "sq_stress")
+        return sig.reshape(n, 6), parts.reshape(n, 18)
+
+    def stress_static(self, cell: int = -1):
+        """sq_stress_static: sq_stress with its sums in the library's static
+        device scratch (no allocation)."""
+        n = len(self._cells(cell))
+        sig = np.zeros(6 * n)
+        parts = np.zeros(18 * n)
+        self._check(self.L.sq_stress_static(self.h, cell, _dp(sig), _dp(parts)), "sq_stress_static")
         return sig.reshape(n, 6), parts.reshape(n, 18)
 
     def pressure(self, cell: int = -1):
