@@ -1,25 +1,29 @@
 #!/usr/bin/env python3
 """SQ node-columns/s including stress, FP64 and mixed precision, on one MI355X.
 
-A step is one pass of the whole hot path over one cell already resident in
-HBM: spectral bounds (FP64 Lanczos), Chebyshev moments, Fermi level,
+A step is one pass of the whole hot path over cells already resident in HBM:
+spectral bounds (FP64 Lanczos), Chebyshev moments, Fermi level,
 Clenshaw-Curtis coefficients and density (sq_density), band energy
-(sq_energy), the kinetic + nonlocal stress pass (sq_stress), the direct
-and trace pressures from its sums (sq_pressure) and the LDA
-exchange-correlation stress term (sq_xc).  The plan
-(grid, atom images, local potential, capacity census) is built before the
-timed region.  Default workload: the 64000-node cell (16 Bohr cube, h = 0.4,
-64 atoms, 21^3 cubes, degree 60, kT = 0.05 Ha).
+(sq_energy), the kinetic + nonlocal stress pass (sq_stress), the direct and
+trace pressures from its sums (sq_pressure) and the LDA exchange-correlation
+stress term (sq_xc).  Each plan (grid, atom images, local potential,
+capacity census, Gram matrices, autotuning) is built before the timed region;
+sq_density and the stress pass are replayed from HIP graphs captured at the
+first (warm-up) call.
 
-Prints one JSON line.  value = node-columns/s of the FP64 path; the mixed
-path (FP32 recurrence vectors, FP64 accumulation) is reported beside it.
+Headline (value): the 64000-node cell (16 Bohr cube, h = 0.4, 64 atoms, 21^3
+cubes, degree 60, kT = 0.05 Ha) on the FP64 path.  Beside it: the same cell
+on the mixed paths, the 32-cell uneven batch (one plan, autotuned) and the
+512000-node cell, each in FP64 and mixed.
+
+Prints one JSON line.
 """
 
 import argparse
 import json
-import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -27,12 +31,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "SQ node-columns/sec incl. stress, FP64 vs mixed precision; % HBM roofline"
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x FMA (2 flop) x 2.4 GHz.  FP64 vector
-# FMAs and unpacked FP32 FMAs issue at the same rate (packed FP32 is not used).
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X: 256 CUs x 4 SIMD x 16 FP64 lanes x FMA (2 flop) x 2.4 GHz
+PEAK_F64_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12     # 78.6
 PEAK_HBM_GBPS = 8000.0
-# LDS: 128 B per clock per CU
-PEAK_LDS_TBPS = 256 * 128 * 2.4e9 / 1e12
 
 # Algorithmic FLOPs of one application of the scaled nodal operator, per cube
 # node: 37-point 12th-order stencil (37 multiply-adds), local potential
@@ -40,14 +41,15 @@ PEAK_LDS_TBPS = 256 * 128 * 2.4e9 / 1e12
 # (node, projector) pair: projection and projector term (2 multiply-adds).
 F_POINT = 2 * 37 + 2 + 2
 F_PAIR = 4
+MU_EVALS = 48   # Fermi-level evaluations launched per sq_density (converged ones skip their reads)
 
 
-def kernel_flops(info, K, stress_fp64=True):
+def kernel_flops(info, stress_fp64=True):
     """Algorithmic FLOPs of the three recurrence kernels for one cell.  The
     FP64 stress pass forms d_q by Clenshaw's recurrence (no per-step
     accumulation); with FP32 vectors it accumulates d_q += c_j t^j in FP64
     (2 FLOP per point and step)."""
-    Nd, nc, npl, pairs = int(info[0]), int(info[1]), int(info[2]), int(info[8])
+    Nd, nc, npl, pairs, K = int(info[0]), int(info[1]), int(info[2]), int(info[8]), int(info[9])
     pts = Nd * nc ** 3
     return {
         "lanczos": K * ((F_POINT + 8) * pts + F_PAIR * pairs),
@@ -56,27 +58,33 @@ def kernel_flops(info, K, stress_fp64=True):
     }
 
 
-def lds_bytes(info, K, word):
+def lds_bytes(info, word):
     """Algorithmic LDS bytes of the three recurrence kernels for one cell:
     the 24 in-plane stencil neighbours of every cube point read from the
     mirror and the point written back, per operator application (word =
     bytes per vector element)."""
-    Nd, nc, npl = int(info[0]), int(info[1]), int(info[2])
+    Nd, nc, npl, K = int(info[0]), int(info[1]), int(info[2]), int(info[9])
     per = Nd * nc ** 3 * 25 * word
     return {"lanczos": K * per, "moments": ((npl + 1) // 2) * per, "stress": npl * per}
 
 
-def hbm_bytes(info, K):
-    """Algorithmic HBM traffic of one step (bytes): the local potential read
-    by every node's cube (once per kernel pass, L2-resident in practice is
-    not assumed), moments written and read, coefficients, records."""
-    Nd, nc, npl = int(info[0]), int(info[1]), int(info[2])
-    v = 8 * Nd * 3                     # potential column reads (three passes), per node column
-    mom = 8 * Nd * (npl + 1) * 2       # moments written, read by coefficients
-    coef = 8 * Nd * (npl + 1) * 2      # coefficients written, read by the stress pass
-    lan = 8 * Nd * 2 * K               # Lanczos tridiagonals
-    rec = 8 * Nd * 24                  # per-node records
-    return v + mom + coef + lan + rec
+def hbm_bytes(info):
+    """Compulsory HBM traffic (bytes), per kernel pass and per step, of one
+    cell: every array read or written once per pass (re-reads within a pass
+    hit the caches: the node's potential columns, its Gram entries at every
+    recurrence step), except the moments, which every Fermi-level evaluation
+    reads again (MU_EVALS, an upper bound: a converged search skips them)."""
+    Nd, nc, npl, K = int(info[0]), int(info[1]), int(info[2]), int(info[9])
+    gram = 12 * int(info[10])                      # value (8) + index pair (4)
+    vloc = 8 * Nd
+    lan = {"lanczos": 8 * Nd * 2 * K + 4 * Nd + gram + vloc,
+           "moments": 8 * Nd * (npl + 1) + 32 * Nd + gram + vloc,
+           "stress": 8 * Nd * (npl + 1) + 32 * Nd + 8 * Nd * 19 + gram + vloc}
+    step = (lan["lanczos"] + lan["moments"] + lan["stress"] +
+            8 * Nd * (npl + 1) * MU_EVALS +           # moments re-read by the Fermi-level search
+            8 * Nd * (npl + 1) * 2 + 8 * Nd * 4 +     # coefficients written; bounds
+            8 * Nd * 24)                               # records of the final reductions
+    return lan, step
 
 
 KERNEL_SOURCES = ("paper_2006_03697_amd/csrc/sq_recur.hip", "paper_2006_03697_amd/csrc/sq_devfn.h",
@@ -94,11 +102,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(phase, precision, workload="64000-node cell, 21^3 cubes, degree 60"):
+def recorded_traffic(phase, precision, workload):
     """HBM bytes per launch of a kernel from the profile summaries (a line
-    'traffic-json: {...}' with the counters of rocprofv3 --pmc FETCH_SIZE and
-    WRITE_SIZE, scaled by the same counters on a plain copy), if they were
-    taken on the current kernel sources; else None."""
+    'traffic-json: {...}' with rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by
+    the same counters on a plain copy), if they were taken on the current
+    kernel sources; else None."""
     import glob
     want = kernel_source_hash()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -114,37 +122,53 @@ def recorded_traffic(phase, precision, workload="64000-node cell, 21^3 cubes, de
     return None
 
 
-def run_precision(sq, cell, precision, steps, warmup):
+def run_plan(sq, cells, precision, steps, warmup, **plan_kw):
+    """Times `steps` whole steps over every cell of one plan (after
+    `warmup`); per-phase device times from the plan's HIP events."""
     import torch
     t0 = time.time()
-    plan = sq.Plan([cell], precision=precision)
+    plan = sq.Plan(cells, precision=precision, **plan_kw)
     setup_s = time.time() - t0
-    info = plan.info[0]
+    info = [i.copy() for i in plan.info]
 
     def step():
-        plan.density_only(0)
-        plan.energy(0)
-        plan.stress(0)
-        plan.pressure(0)
-        plan.xc(0)
+        plan.density_only(-1)
+        plan.energy(-1)
+        plan.stress(-1)
+        plan.pressure(-1)
+        plan.xc(-1)
 
-    for _ in range(warmup):
+    label = "%d cell%s, %d nodes, %s" % (len(cells), "" if len(cells) == 1 else "s",
+                                         sum(int(i[0]) for i in info), precision)
+    for k in range(warmup):
+        ta = time.perf_counter()
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print("bench:   warm-up %d (%s): %.2f s" % (k, label, time.perf_counter() - ta), file=sys.stderr, flush=True)
     plan.phase_times(reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    times = []
+    for k in range(steps):
+        ta = time.perf_counter()
         step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ta)
+        if steps <= 3 or times[-1] > 5.0:
+            print("bench:   step %d (%s): %.2f s" % (k, label, times[-1]), file=sys.stderr, flush=True)
     ph = plan.phase_times(reset=True)
-    _, mu = plan.density(0)
-    sig, _ = plan.stress(0)
-    pd, pt = plan.pressure(0)
+    _, mu = plan.density(-1)
+    sig, _ = plan.stress(-1)
+    pd, pt = plan.pressure(-1)
     plan.close()
-    ms = (t1 - t0) * 1000.0 / steps
-    return dict(ms=ms, setup_s=setup_s, info=info, phases=ph, mu=float(mu[0]),
-                sigma=[float(x) for x in sig[0]], p_direct=float(pd[0]), p_trace=float(pt[0]))
+    times.sort()
+    ms = 1000.0 * times[len(times) // 2]   # median step
+    nodes = sum(int(i[0]) for i in info)
+    return dict(ms=ms, ms_mean=1000.0 * sum(times) / len(times), setup_s=setup_s, info=info,
+                nodes=nodes, phases=ph, mu=[float(x) for x in mu], sigma=[[float(x) for x in s] for s in sig],
+                p_direct=[float(x) for x in pd], p_trace=[float(x) for x in pt])
+
+
+def per_launch(res):
+    return {k: v[0] / max(v[1], 1) for k, v in res["phases"].items()}
 
 
 def cpu_baseline(cell, mu, sample):
@@ -172,11 +196,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=8192,
                     help="nodes in the oracle's CPU-baseline sample (0: skip)")
-    ap.add_argument("--precision", choices=["both", "fp64", "mixed", "mixed_stress"], default="both",
-                    help="both: fp64 (the headline value), mixed and mixed_stress beside it")
-    ap.add_argument("--npl", type=int, default=60,
-                    help="Chebyshev degree of the 64000-node cell (60; the mixed-precision "
-                         "sweep of the same cell uses 40 and 80 as well)")
+    ap.add_argument("--precision", choices=["all", "fp64", "mixed", "mixed_stress"], default="all",
+                    help="all: fp64 (the headline value), mixed and mixed_stress beside it")
+    ap.add_argument("--npl", type=int, default=60, help="Chebyshev degree of the 64000-node cell")
+    ap.add_argument("--extra", type=int, default=1,
+                    help="1: also the 32-cell batch and the 512000-node cell (one timed step each)")
+    ap.add_argument("--eager", action="store_true", help="launch eagerly instead of replaying graphs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit: "
                          "the reference for scaling the HBM byte counters of a profiler")
@@ -200,27 +225,41 @@ def main():
     from paper_2006_03697_amd import sq
     from paper_2006_03697_amd import workloads as W
     sq.load()
+    graph = not args.eager
+    # measured LDS read peaks (16-byte reads: the FP64 mirror; 8-byte: FP32)
+    lds_peak = {w: sq.probe_lds(w) for w in (16, 8)}
+    print("bench: LDS peak %s" % {w: "%.1f TB/s" % v[0] for w, v in lds_peak.items()}, file=sys.stderr, flush=True)
+
     cell = W.fp64_cell(npl=args.npl)
-    K = int(cell["lanczos_steps"])
     res = {}
-    for prec in (["fp64", "mixed", "mixed_stress"] if args.precision == "both" else [args.precision]):
-        res[prec] = run_precision(sq, cell, prec, args.steps, args.warmup)
-        print("bench: %s %.2f ms/step  phases %s" % (
-            prec, res[prec]["ms"], {k: round(v[0] / max(v[1], 1), 3) for k, v in res[prec]["phases"].items()}),
+    precs = ["fp64", "mixed", "mixed_stress"] if args.precision == "all" else [args.precision]
+    for prec in precs:
+        res[prec] = run_plan(sq, [cell], prec, args.steps, args.warmup, use_graph=graph)
+        if graph:
+            # graph replays record no per-phase events: the kernel times come
+            # from an eager run of the same kernels (same stream, HIP events)
+            eag = run_plan(sq, [cell], prec, min(args.steps, 3), 1)
+            res[prec]["phases"] = eag["phases"]
+            res[prec]["eager_ms"] = eag["ms"]
+        print("bench: 64000-node cell %s %.2f ms/step  phases %s" % (
+            prec, res[prec]["ms"], {k: round(v, 3) for k, v in per_launch(res[prec]).items()}),
             file=sys.stderr, flush=True)
 
-    head = "fp64" if "fp64" in res else next(iter(res))
+    head = precs[0]
     r = res[head]
-    info = r["info"]
+    info = r["info"][0]
     Nd = int(info[0])
-    flops = kernel_flops(info, K, stress_fp64=head == "fp64")
-    per_launch = {k: r["phases"][k][0] / max(r["phases"][k][1], 1) for k in flops}
-    dom = max(per_launch, key=lambda k: per_launch[k])
-    achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
-    step_bytes = hbm_bytes(info, K)
-    # bytes per vector element of the dominant kernel in the head precision
-    word = 8 if head == "fp64" or (head == "mixed_stress" and dom != "stress") else 4
-    lds_tbps = lds_bytes(info, K, word)[dom] / (per_launch[dom] * 1e-3) / 1e12
+    fp64 = head == "fp64"
+    flops = kernel_flops(info, stress_fp64=fp64)
+    pl = per_launch(r)
+    dom = max(flops, key=lambda k: pl[k])
+    achieved = flops[dom] / (pl[dom] * 1e-3) / 1e12
+    wl = "64000-node cell, 21^3 cubes, degree %d" % int(info[2])
+    # LDS: FP64 mirror elements are 16 bytes (two planes), FP32 ones 8 bytes
+    word = 8 if fp64 or (head == "mixed_stress" and dom != "stress") else 4
+    lds_w = 16 if word == 8 else 8
+    lds_tbps = lds_bytes(info, word)[dom] / (pl[dom] * 1e-3) / 1e12
+    hb_launch, hb_step = hbm_bytes(info)
     out = {
         "metric": METRIC,
         "value": Nd / (r["ms"] * 1e-3),
@@ -232,42 +271,70 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": "f64" if fp64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "periodic 16 Bohr cube, h 0.4 (40^3 = 64000 nodes), 64 atoms "
                                "(seed 1, min spacing 1.5), R_cut 4 (21^3 cubes), degree %d, "
-                               "kT 0.05 Ha, 12th-order FD, Lanczos K=%d" % (int(info[2]), K),
-                   "nodes": Nd, "cube": int(info[1]) ** 3, "npl": int(info[2]),
-                   "precision": head},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved,
-                     "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS,
-                     "traffic": recorded_traffic(dom, head, "64000-node cell, 21^3 cubes, degree %d"
-                                                 % int(info[2]))},
-        "lds": {"kernel": dom, "achieved": lds_tbps, "peak": PEAK_LDS_TBPS, "unit": "TB/s",
-                "frac": lds_tbps / PEAK_LDS_TBPS},
-        "hbm": {"achieved": step_bytes / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS,
-                "unit": "GB/s", "frac": step_bytes / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS},
-        "phases_ms": {k: v[0] / max(v[1], 1) for k, v in r["phases"].items()},
+                               "kT 0.05 Ha, 12th-order FD, Lanczos K=%d" % (int(info[2]), int(info[9])),
+                   "nodes": Nd, "cube": int(info[1]) ** 3, "npl": int(info[2]), "precision": head,
+                   "launch": "graph replay" if graph else "eager"},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_F64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_F64_TFLOPS,
+                     "traffic": recorded_traffic(dom, head, wl),
+                     "algorithmic_flop_per_launch": flops[dom], "launch_ms": pl[dom]},
+        "lds": {"kernel": dom, "achieved": lds_tbps, "peak": lds_peak[lds_w][0], "unit": "TB/s",
+                "frac": lds_tbps / lds_peak[lds_w][0],
+                "peak_kind": "measured, conflict-free %d-byte reads (sq_probe_lds)" % lds_w},
+        "hbm": {"achieved": hb_step / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": hb_step / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS,
+                "kind": "algorithmic (compulsory) bytes per step", "bytes_per_step": hb_step,
+                "dominant_kernel_bytes_per_launch": hb_launch[dom]},
+        "phases_ms": pl,
+        "eager_ms_per_step": r.get("eager_ms", r["ms"]),
         "setup_s": r["setup_s"],
-        "pressure": {"direct": r["p_direct"], "trace": r["p_trace"], "unit": "Ha/Bohr^3"},
+        "pressure": {"direct": r["p_direct"][0], "trace": r["p_trace"][0], "unit": "Ha/Bohr^3"},
     }
     for mk in ("mixed", "mixed_stress"):
         if mk not in res or head != "fp64":
             continue
         m = res[mk]
-        mf = kernel_flops(m["info"], K, stress_fp64=False)
-        mpl = {k: m["phases"][k][0] / max(m["phases"][k][1], 1) for k in mf}
+        mf = kernel_flops(m["info"][0], stress_fp64=False)
+        mpl = per_launch(m)
         out[mk] = {"value": Nd / (m["ms"] * 1e-3), "ms_per_step": m["ms"], "dtype": "f32+f64",
                    "vectors": "f32 both passes" if mk == "mixed" else "f64 moments, f32 stress pass",
-                   "speedup_vs_fp64": r["ms"] / m["ms"],
-                   "phases_ms": {k: v[0] / max(v[1], 1) for k, v in m["phases"].items()},
+                   "speedup_vs_fp64": r["ms"] / m["ms"], "phases_ms": mpl,
                    "stress_tflops": mf["stress"] / (mpl["stress"] * 1e-3) / 1e12,
-                   "mu_diff_vs_fp64": abs(m["mu"] - r["mu"]),
-                   "sigma_diff_vs_fp64": max(abs(a - b) for a, b in zip(m["sigma"], r["sigma"])),
-                   "p_direct_diff_vs_fp64": abs(m["p_direct"] - r["p_direct"])}
+                   "mu_diff_vs_fp64": abs(m["mu"][0] - r["mu"][0]),
+                   "sigma_diff_vs_fp64": max(abs(a - b) for a, b in zip(m["sigma"][0], r["sigma"][0])),
+                   "p_direct_diff_vs_fp64": abs(m["p_direct"][0] - r["p_direct"][0])}
+
+    if args.extra:
+        tune = os.path.join(tempfile.gettempdir(), "sq_bench_tune.json")
+        extra = {"batched_32_cells": (W.batched_cells(n_cells=32, seed=3),
+                                      dict(use_graph=graph, autotune=True, tune_cache=tune)),
+                 "large_512000_nodes": ([W.large_cell()], dict(use_graph=graph))}
+        for name, (cells, kw) in extra.items():
+            e = {}
+            for prec in ("fp64", "mixed"):
+                x = run_plan(sq, cells, prec, 1, 1, **kw)
+                e[prec] = {"value": x["nodes"] / (x["ms"] * 1e-3), "ms_per_step": x["ms"],
+                           "setup_s": x["setup_s"]}
+                print("bench: %s %s %.1f ms/step (set-up %.1f s)" % (name, prec, x["ms"], x["setup_s"]),
+                      file=sys.stderr, flush=True)
+                if prec == "fp64":
+                    s64 = x["sigma"]
+                else:
+                    e["sigma_diff_vs_fp64"] = max(abs(a - b) for s, t in zip(x["sigma"], s64)
+                                                  for a, b in zip(s, t))
+                e["nodes"] = x["nodes"]
+            e["speedup_mixed_vs_fp64"] = e["fp64"]["ms_per_step"] / e["mixed"]["ms_per_step"]
+            e["unit"] = "node-columns/s"
+            e["launch"] = ("graph replay" if graph else "eager") + (", autotuned" if kw.get("autotune") else "")
+            e["steps"] = 1
+            out[name] = e
+
     if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(cell, r["mu"], args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(cell, r["mu"][0], args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 

@@ -112,7 +112,7 @@ typedef struct {
  *                      graph on hip_stream afterwards (the host only reads
  *                      back the Fermi level, the error flags and the sums).
  *   autotune           1: at set-up, time the kernel variants of every
- *                      node group (slot capacity 16 with the projector
+ *                      node group (slot capacity 16 or 24 with the projector
  *                      weights of plane 0 in registers, or 48 recomputing
  *                      them; persistent or one-workgroup-per-node launch) on
  *                      a sample of its nodes and keep the fastest per kernel;
@@ -256,12 +256,16 @@ sq_status sq_moments(sq_plan plan, int cell, const int64_t* nodes, int64_t n, do
  * the steps taken), K = the cell's lanczos_steps.  Needs sq_density. */
 sq_status sq_lanczos(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
-/* Plan queries (info has 10 entries): info[0] = N_d, info[1] = n_c,
+/* Plan queries (info has 12 entries): info[0] = N_d, info[1] = n_c,
  * info[2] = npl, info[3] = number of atom images, info[4] = max images in a
  * node tile, info[5..7] = largest number of images reaching one cube,
  * crossing one cube column, and nonzero at one node, info[8] = number of
  * (node, projector) pairs over all nodes' cubes (measured at set-up),
- * info[9] = the Lanczos step count K in effect (lanczos_steps, 0 -> 20). */
+ * info[9] = the Lanczos step count K in effect (lanczos_steps, 0 -> 20),
+ * info[10] = stored Gram-matrix entries over the cell's nodes (each read
+ * at every recurrence step of its node: 12 bytes per entry), info[11] =
+ * nodes whose Gram matrix is stored (one projector sweep per step; the
+ * others take two). */
 sq_status sq_cell_info(sq_plan plan, int cell, int64_t* info);
 
 /* Device time of each phase accumulated over the calls since the last reset

@@ -36,6 +36,7 @@ struct CellHost {
   // node; (node, projector) pairs
   int census_img = 0, census_col = 0, census_near = 0;
   long long census_pairs = 0;
+  long long gram_entries = 0, gram_nodes = 0;   // stored Gram entries; nodes on the single-sweep form
   double c2[SQ_FDM + 1], c1[SQ_FDM + 1];
   double* d_vloc = nullptr;
   double* d_img = nullptr;
@@ -45,7 +46,7 @@ struct CellHost {
 
 // Variant of one kernel family on a node group.
 struct Tile {
-  int kc = 0;           // slot capacity (16: plane-0 weights in registers, 48: recomputed); 0: smallest
+  int kc = 0;           // slot capacity (16, 24: plane-0 weights in registers, 48: recomputed); 0: smallest
   int persistent = 0;   // persistent grid with a work counter
 };
 
@@ -626,7 +627,7 @@ void tune_read(sq_plan p, const char* path) {
     const size_t lb = text.find('[', end), rb = text.find(']', end);
     if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
     int kc = 0, per = 0;
-    if (std::sscanf(text.c_str() + lb + 1, "%d , %d", &kc, &per) == 2 && (kc == 16 || kc == 48) &&
+    if (std::sscanf(text.c_str() + lb + 1, "%d , %d", &kc, &per) == 2 && (kc == 16 || kc == 24 || kc == 48) &&
         (per == 0 || per == 1)) {
       Tile t;
       t.kc = kc;
@@ -685,8 +686,8 @@ sq_status time_tile(sq_plan p, const Group& g, int fam, const Tile& t, const lon
 }
 
 // Picks, per group of the whole-plan selection and kernel family, the
-// fastest variant (slot capacity 16 with the plane-0 weights in registers,
-// or 48 recomputing them; persistent or one workgroup per node) on a sample
+// fastest variant (slot capacity 16 or 24 with the plane-0 weights in
+// registers, or 48 recomputing them; persistent or one workgroup per node) on a sample
 // of the group's nodes (its first nodes: the
 // longest).  The sample's bounds come from the tuned Lanczos, and its
 // coefficients are zero for the stress timing (the operation count does not
@@ -700,7 +701,7 @@ sq_status autotune(sq_plan p) {
     if (all_known) continue;
     const long long n = std::min<long long>(g.n, 2048);
     std::vector<Tile> cand;
-    for (int kc : {16, 48})
+    for (int kc : {16, 24, 48})
       for (int per = 0; per <= 1; ++per) {
         Tile t;
         t.kc = kc;
@@ -989,6 +990,16 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
       st = check_hip(p, hipMemcpyAsync(gn.data(), P.gn, sizeof(int) * N, hipMemcpyDeviceToHost, p->stream),
                      "gram copy");
     if (st == SQ_OK) st = check_errors(p);
+    for (int i = 0; i < n_cells && st == SQ_OK; ++i) {
+      CellHost& c = p->cells[i];
+      for (long long q = 0; q < c.Nd; ++q) {
+        const int k = gn[c.node_base + q];
+        if (k >= 0) {
+          c.gram_entries += k;
+          c.gram_nodes += 1;
+        }
+      }
+    }
     if (st == SQ_OK) st = make_selection(p, all, p->all, &gn);
     p->per_cell.resize(n_cells);
     for (int i = 0; i < n_cells && st == SQ_OK; ++i) st = make_selection(p, {i}, p->per_cell[i], &gn);
@@ -1069,6 +1080,8 @@ sq_status sq_cell_info(sq_plan p, int cell, int64_t* info) {
   info[7] = c.census_near;
   info[8] = c.census_pairs;
   info[9] = c.K;
+  info[10] = c.gram_entries;
+  info[11] = c.gram_nodes;
   return SQ_OK;
 }
 

@@ -153,10 +153,10 @@ SQ_NC_LIST(SQ_DECL_NC)
 __host__ __device__ constexpr int sq_threads(int nc) { return ((nc * nc + 63) / 64) * 64; }
 
 // Slot capacities compiled per single-sweep form: the smallest that holds
-// kc (16: plane-0 weights kept in registers; 48: recomputed); two-sweep
-// nodes: 48.  0: none.
+// kc (16 and 24: plane-0 weights kept in registers; 48: recomputed);
+// two-sweep nodes: 48.  0: none.
 __host__ __device__ constexpr int sq_kc_pick(bool fused, int kc) {
-  return !fused ? (kc <= 48 ? 48 : 0) : (kc <= 16 ? 16 : (kc <= 48 ? 48 : 0));
+  return !fused ? (kc <= 48 ? 48 : 0) : (kc <= 16 ? 16 : (kc <= 24 ? 24 : (kc <= 48 ? 48 : 0)));
 }
 
 // Largest number of atom images one cube may see (the image index shares a

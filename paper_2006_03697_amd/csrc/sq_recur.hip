@@ -1512,7 +1512,7 @@ hipError_t launch_var(const RecLaunch& R, const PlanDev& P, const long long* ite
 }
 
 // The compiled variants per precision: sq_kc_pick gives the slot capacity
-// (16 with the plane weights in registers, or 48); nodes without a stored
+// (16 or 24 with the plane weights in registers, or 48); nodes without a stored
 // Gram matrix (rare: dense projector overlap) all use the 48-slot two-sweep
 // form.  The persistent form is compiled for the 16-slot single-sweep
 // variant; the others run one workgroup per node.
@@ -1525,6 +1525,7 @@ hipError_t launch_t(const RecLaunch& R, const PlanDev& P, const long long* items
     return hipErrorInvalidValue;
   }
   if (kc == 16) return launch_var<Var<T, SQN, 16, true>, F, true, true>(R, P, items, ic, n, s);
+  if (kc == 24) return launch_var<Var<T, SQN, 24, true>, F, true, false>(R, P, items, ic, n, s);
   if (kc == 48) return launch_var<Var<T, SQN, 48, false>, F, true, false>(R, P, items, ic, n, s);
   return hipErrorInvalidValue;
 }

@@ -109,13 +109,19 @@ def test_bench_algorithmic_counts():
     import sys
     sys.path.insert(0, ROOT)
     import bench
-    info = [64000, 21, 60, 0, 0, 0, 0, 0, 1000]
+    info = [64000, 21, 60, 0, 0, 0, 0, 0, 1000, 20, 5000, 64000]
     pts = 64000 * 21 ** 3
-    f = bench.kernel_flops(info, 20)
+    f = bench.kernel_flops(info)
     assert f["stress"] == 60 * (78 * pts + 4 * 1000)
-    assert bench.kernel_flops(info, 20, stress_fp64=False)["stress"] == 60 * (80 * pts + 4 * 1000)
+    assert bench.kernel_flops(info, stress_fp64=False)["stress"] == 60 * (80 * pts + 4 * 1000)
     assert f["moments"] == 30 * (82 * pts + 4 * 1000)
     assert f["lanczos"] == 20 * (86 * pts + 4 * 1000)
-    assert bench.lds_bytes(info, 20, 8)["stress"] == 60 * pts * 25 * 8
+    assert bench.lds_bytes(info, 8)["stress"] == 60 * pts * 25 * 8
+    per, step = bench.hbm_bytes(info)
+    # the stress pass reads the coefficients, bounds, Gram entries (12 bytes
+    # each) and potential once, and writes 19 record columns
+    assert per["stress"] == 8 * 64000 * 61 + 32 * 64000 + 8 * 64000 * 19 + 12 * 5000 + 8 * 64000
+    # every Fermi-level evaluation re-reads the moments
+    assert step > bench.MU_EVALS * 8 * 64000 * 61
     # a traffic record is used only for the kernel sources it was taken on
     assert bench.recorded_traffic("stress", "fp64", "no such workload") is None
