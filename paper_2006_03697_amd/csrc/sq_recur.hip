@@ -163,6 +163,15 @@ struct Var {
   // elements of the cube buffer: the mirror, or the Gram scratch
   static constexpr size_t GEL = (GSCR + sizeof(V) - 1) / sizeof(V);
   static constexpr size_t TLN = GEL > (size_t)L::SIZE ? GEL : (size_t)L::SIZE;
+  // copies of the projection sums: lanes of a wave that add to the same
+  // image serialise on its LDS words, so lane l adds to copy l mod NCOPY
+  // (copies of one image are adjacent, in distinct banks) and the copies
+  // are summed after the step; as many as the LDS left over holds (1..8)
+  static constexpr size_t USED = sizeof(V) * (size_t)TLN + OTHER;
+  static constexpr int NCOPY = USED + 16 * 7 * (size_t)NIMG <= 163840   ? 8
+                               : USED + 16 * 3 * (size_t)NIMG <= 163840 ? 4
+                               : USED + 16 * 1 * (size_t)NIMG <= 163840 ? 2
+                                                                        : 1;
 };
 
 template <class Vr>
@@ -180,7 +189,7 @@ struct Smem {
   double pf[2][NI];                   // projections <chi_I, v>, double-buffered over steps
   double gpf[2][NI];                  // gamma dV <chi_I, v>
   union {
-    unsigned long long pint[NI][2];   // projection sums being formed (two-word integers)
+    unsigned long long pint[NI][Vr::NCOPY][2];   // projection sums being formed (copies, two words)
     // stress pass, after the last step: G_b = grad_b d on the line through
     // the node along a
     double kl[3][3][2 * SQ_FDM + 1];
@@ -372,8 +381,11 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     S.pf[1][i] = 0.0;
     S.gpf[0][i] = 0.0;
     S.gpf[1][i] = 0.0;
-    S.pint[i][0] = 0ull;
-    S.pint[i][1] = 0ull;
+#pragma unroll
+    for (int c = 0; c < Vr::NCOPY; ++c) {
+      S.pint[i][c][0] = 0ull;
+      S.pint[i][c][1] = 0ull;
+    }
   }
   for (int i = tid; i < (int)Vr::TLN; i += NT) S.tl[i] = typename Vr::V{};
   if (tid == 0) S.nnear = 0;
@@ -491,7 +503,7 @@ __device__ __forceinline__ void project(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& 
       slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
                          [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
       // a slot past the thread's count has sid 0 and weight zero: it adds 0 to image 0
-      fx_add(S.pint[i], (double)part, X.bad);
+      fx_add(S.pint[i][threadIdx.x & (Vr::NCOPY - 1)], (double)part, X.bad);
     }
   }
 }
@@ -503,13 +515,19 @@ __device__ __forceinline__ void project(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& 
 template <class Vr>
 __device__ __forceinline__ void finish_proj(Smem<Vr>& S, int par, double alpha = 0.0, double ib = 1.0) {
   for (int i = threadIdx.x; i < Vr::NIMG; i += Vr::NT) {
-    double v = fx_load(S.pint[i]);
+    unsigned long long hi = 0ull, lo = 0ull;
+#pragma unroll
+    for (int c = 0; c < Vr::NCOPY; ++c) {
+      hi += S.pint[i][c][0];
+      lo += S.pint[i][c][1];
+      S.pint[i][c][0] = 0ull;
+      S.pint[i][c][1] = 0ull;
+    }
+    double v = fx_join((long long)hi, (long long)lo);
     if (alpha != 0.0) v -= alpha * S.pf[par][i];
     v *= ib;
     S.pf[par ^ 1][i] = v;
     S.gpf[par ^ 1][i] = S.gdv[i] * v;
-    S.pint[i][0] = 0ull;
-    S.pint[i][1] = 0ull;
   }
 }
 
@@ -563,7 +581,7 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
           const double gval = X.gvp[kk];
           const unsigned ij = in ? X.gip[kk] : 0u;
           const int i = (int)(ij & 0xffffu), j = (int)(ij >> 16);
-          fx_add(S.pint[i], in ? gval * (sc * S.gpf[par][j]) : 0.0, X.bad);
+          fx_add(S.pint[i][threadIdx.x & (Vr::NCOPY - 1)], in ? gval * (sc * S.gpf[par][j]) : 0.0, X.bad);
         }
       }
     }
@@ -633,7 +651,7 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
                          part += w * io[z];
                          io[z] += w * coef;
                        });
-        fx_add(S.pint[i], (double)part, X.bad);
+        fx_add(S.pint[i][threadIdx.x & (Vr::NCOPY - 1)], (double)part, X.bad);
       }
     }
   } else {
