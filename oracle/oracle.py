@@ -36,7 +36,11 @@ Readings of what the paper leaves open (also listed in the design notes):
   R17 LDA exchange-correlation: Slater exchange, Perdew-Wang 1992
      correlation (unpolarised); nodes with rho <= 0 contribute nothing.
 Parity unpinned (problem-definition choices, no external value fixes them):
-the Lanczos step count / widening rule (R1) and the cutoffs (R8).
+the Lanczos step count / widening rule (R1) and the cutoffs (R8).  The
+Perdew-Wang parameters are pinned through the uniform-gas expansion
+constants they were fitted to reproduce (A, b1, b2 by the high-density
+c0, c1 and the absent sqrt(rs) term; a1, b3, b4 by c2, d0 = a1/b4 and
+d1 = a1 b3/b4^2, to the digits those constants are printed with).
 """
 
 from __future__ import annotations
