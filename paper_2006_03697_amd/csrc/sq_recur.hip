@@ -142,9 +142,15 @@ struct Var {
   static constexpr int GPT = (GCAP + NT - 1) / NT;   // Gram entries per thread (registers)
   static_assert(NIMG <= (1 << IBITS) && NIMG <= 65536, "image index width");
   static_assert(NT <= 1024, "workgroup size");
-  static constexpr size_t OTHER = 8 * (size_t)NIMG * 9 + 8 * 4 * (size_t)NIMG +
-                                  16 * (size_t)NIMG + 16 * (size_t)NEAR * 10 + (size_t)NEAR * 12 +
-                                  2 * 2 * 16 * 8 + 256;   // the stress line buffer shares pint's space
+  // LDS besides the cube buffer: per-image tables, near images, block sums,
+  // and a union of the projection sums (steps) with the stress pass's
+  // near-image sums and line buffer (after the last step)
+  static constexpr size_t OTHER = 8 * (size_t)NIMG * 9 + 8 * 4 * (size_t)NIMG + (size_t)NEAR * 12 +
+                                  2 * 2 * 16 * 8 + 256;
+  static constexpr size_t EPB = 16 * (size_t)NEAR * 10 + 8 * 9 * (2 * SQ_FDM + 1);
+  static constexpr size_t uni(int copies) {
+    return 16 * (size_t)NIMG * copies > EPB ? 16 * (size_t)NIMG * copies : EPB;
+  }
   // scratch of the Gram build in the cube buffer: pair bitmap [NIMG][NWD],
   // row starts [NIMG + 1], slot words [KC][NT], two-word sums [GCAP][2]
   static constexpr int NWD = (NIMG + 31) / 32;
@@ -156,7 +162,7 @@ struct Var {
 #ifdef SQ_NO_PAD
   static constexpr bool PAD = false;
 #else
-  static constexpr bool PAD = sizeof(V) * (size_t)Lay<NC_, G, M, true>::SIZE + OTHER <= 163840;
+  static constexpr bool PAD = sizeof(V) * (size_t)Lay<NC_, G, M, true>::SIZE + OTHER + uni(1) <= 163840;
 #endif
   using L = Lay<NC_, G, M, PAD>;
   static constexpr int MH = NC_ / 2;
@@ -168,10 +174,10 @@ struct Var {
   // (copies of one image are adjacent, in distinct banks) and the copies
   // are summed after the step; as many as the LDS left over holds (1..8)
   static constexpr size_t USED = sizeof(V) * (size_t)TLN + OTHER;
-  static constexpr int NCOPY = USED + 16 * 7 * (size_t)NIMG <= 163840   ? 8
-                               : USED + 16 * 3 * (size_t)NIMG <= 163840 ? 4
-                               : USED + 16 * 1 * (size_t)NIMG <= 163840 ? 2
-                                                                        : 1;
+  static constexpr int NCOPY = USED + uni(8) <= 163840   ? 8
+                               : USED + uni(4) <= 163840 ? 4
+                               : USED + uni(2) <= 163840 ? 2
+                                                         : 1;
 };
 
 template <class Vr>
@@ -190,11 +196,11 @@ struct Smem {
   double gpf[2][NI];                  // gamma dV <chi_I, v>
   union {
     unsigned long long pint[NI][Vr::NCOPY][2];   // projection sums being formed (copies, two words)
-    // stress pass, after the last step: G_b = grad_b d on the line through
-    // the node along a
-    double kl[3][3][2 * SQ_FDM + 1];
+    struct {   // stress pass, after the last step
+      unsigned long long nsum[Vr::NEAR][10][2];  // sums over the near images' supports
+      double kl[3][3][2 * SQ_FDM + 1];           // G_b = grad_b d on the line through the node along a
+    } ep;
   };
-  unsigned long long nsum[Vr::NEAR][10][2];   // stress pass: sums over near images' supports
   double red[2][2 * 16];              // block sums, double-buffered over steps
   double near_chi[Vr::NEAR];
   int near_img[Vr::NEAR];
@@ -1221,10 +1227,10 @@ __device__ __forceinline__ void near_sums(Smem<Vr>& S, Ctx<Vr>& X, const CellDev
                              }
                            });
         if constexpr (DIR < 0) {
-          fx_add(S.nsum[nidx][0], acc[0], X.bad);
+          fx_add(S.ep.nsum[nidx][0], acc[0], X.bad);
         } else {
 #pragma unroll
-          for (int b = 0; b < 3; ++b) fx_add(S.nsum[nidx][1 + 3 * DIR + b], acc[b], X.bad);
+          for (int b = 0; b < 3; ++b) fx_add(S.ep.nsum[nidx][1 + 3 * DIR + b], acc[b], X.bad);
         }
       }
     }
@@ -1335,8 +1341,8 @@ __global__ void __launch_bounds__(Vr::NT) k_stress(PlanDev P, const long long* i
       }
       S.nnear = nn < Vr::NEAR ? nn : Vr::NEAR;
     }
-    for (int i = threadIdx.x; i < Vr::NEAR * 10 * 2; i += Vr::NT) (&S.nsum[0][0][0])[i] = 0ull;
-    for (int i = threadIdx.x; i < 3 * 3 * (2 * SQ_FDM + 1); i += Vr::NT) (&S.kl[0][0][0])[i] = 0.0;
+    for (int i = threadIdx.x; i < Vr::NEAR * 10 * 2; i += Vr::NT) (&S.ep.nsum[0][0][0])[i] = 0ull;
+    for (int i = threadIdx.x; i < 3 * 3 * (2 * SQ_FDM + 1); i += Vr::NT) (&S.ep.kl[0][0][0])[i] = 0.0;
     __syncthreads();
     near_sums<Vr, -1>(S, X, C, d);   // chi^T d
 #pragma unroll
@@ -1364,9 +1370,9 @@ __global__ void __launch_bounds__(Vr::NT) k_stress(PlanDev P, const long long* i
 #pragma unroll
         for (int z = 0; z < ZH; ++z) {
           const int ox = X.cx - m, oy = X.cy - m, oz = z - m;
-          if (oy == 0 && oz == 0 && ox >= -SQ_FDM && ox <= SQ_FDM) S.kl[0][dir][ox + SQ_FDM] = gr[z];
-          if (ox == 0 && oz == 0 && oy >= -SQ_FDM && oy <= SQ_FDM) S.kl[1][dir][oy + SQ_FDM] = gr[z];
-          if (ox == 0 && oy == 0 && oz >= -SQ_FDM && oz <= SQ_FDM) S.kl[2][dir][oz + SQ_FDM] = gr[z];
+          if (oy == 0 && oz == 0 && ox >= -SQ_FDM && ox <= SQ_FDM) S.ep.kl[0][dir][ox + SQ_FDM] = gr[z];
+          if (ox == 0 && oz == 0 && oy >= -SQ_FDM && oy <= SQ_FDM) S.ep.kl[1][dir][oy + SQ_FDM] = gr[z];
+          if (ox == 0 && oy == 0 && oz >= -SQ_FDM && oz <= SQ_FDM) S.ep.kl[2][dir][oz + SQ_FDM] = gr[z];
         }
       }
       if (dir == 0) near_sums<Vr, 0>(S, X, C, gr);
@@ -1381,7 +1387,7 @@ __global__ void __launch_bounds__(Vr::NT) k_stress(PlanDev P, const long long* i
       for (int a = 0; a < 3; ++a)
         for (int bb = 0; bb < 3; ++bb) {
           double acc = 0.0;
-          for (int k = 1; k <= SQ_FDM; ++k) acc += w[k] * (S.kl[a][bb][SQ_FDM + k] - S.kl[a][bb][SQ_FDM - k]);
+          for (int k = 1; k <= SQ_FDM; ++k) acc += w[k] * (S.ep.kl[a][bb][SQ_FDM + k] - S.ep.kl[a][bb][SQ_FDM - k]);
           rec[2 + 3 * a + bb] = 2.0 * acc * ih;
         }
       double N[9], enl = 0.0;
@@ -1391,7 +1397,7 @@ __global__ void __launch_bounds__(Vr::NT) k_stress(PlanDev P, const long long* i
         const int i = S.near_img[n];
         const double f = -2.0 * S.gdv[i] * S.near_chi[n];
         double ns[10];
-        for (int t = 0; t < 10; ++t) ns[t] = fx_load(S.nsum[n][t]);
+        for (int t = 0; t < 10; ++t) ns[t] = fx_load(S.ep.nsum[n][t]);
         enl -= f * ns[0];   // 2 gamma dV chi_I(x_q) chi_I^T d_q
         for (int a = 0; a < 3; ++a)
           for (int bb = 0; bb < 3; ++bb) N[3 * a + bb] += f * ((a == bb ? ns[0] : 0.0) + 2.0 * ns[1 + 3 * a + bb]);
