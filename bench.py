@@ -44,28 +44,39 @@ F_PAIR = 4
 MU_EVALS = 48   # Fermi-level evaluations launched per sq_density (converged ones skip their reads)
 
 
+def lanczos_run(info):
+    """(Lanczos steps run per node, moments from the Lanczos tridiagonal)."""
+    if len(info) > 13:
+        return int(info[12]), bool(info[13])
+    return int(info[9]), False
+
+
 def kernel_flops(info, stress_fp64=True):
-    """Algorithmic FLOPs of the three recurrence kernels for one cell.  The
-    FP64 stress pass forms d_q by Clenshaw's recurrence (no per-step
+    """Algorithmic FLOPs of the recurrence kernels for one cell.  The FP64
+    stress pass forms d_q by Clenshaw's recurrence (no per-step
     accumulation); with FP32 vectors it accumulates d_q += c_j t^j in FP64
-    (2 FLOP per point and step)."""
-    Nd, nc, npl, pairs, K = int(info[0]), int(info[1]), int(info[2]), int(info[8]), int(info[9])
+    (2 FLOP per point and step).  Moments from the Lanczos tridiagonal cost
+    7 FLOP per component of the (k + 1)-vector and degree."""
+    Nd, nc, npl, pairs = int(info[0]), int(info[1]), int(info[2]), int(info[8])
+    kr, quad = lanczos_run(info)
     pts = Nd * nc ** 3
     return {
-        "lanczos": K * ((F_POINT + 8) * pts + F_PAIR * pairs),
-        "moments": ((npl + 1) // 2) * ((F_POINT + 4) * pts + F_PAIR * pairs),
+        "lanczos": kr * ((F_POINT + 8) * pts + F_PAIR * pairs),
+        "moments": (Nd * npl * 7 * (kr + 1) if quad else
+                    ((npl + 1) // 2) * ((F_POINT + 4) * pts + F_PAIR * pairs)),
         "stress": npl * ((F_POINT + (0 if stress_fp64 else 2)) * pts + F_PAIR * pairs),
     }
 
 
 def lds_bytes(info, word):
-    """Algorithmic LDS bytes of the three recurrence kernels for one cell:
-    the 24 in-plane stencil neighbours of every cube point read from the
-    mirror and the point written back, per operator application (word =
-    bytes per vector element)."""
-    Nd, nc, npl, K = int(info[0]), int(info[1]), int(info[2]), int(info[9])
+    """Algorithmic LDS bytes of the recurrence kernels for one cell: the 24
+    in-plane stencil neighbours of every cube point read from the mirror and
+    the point written back, per operator application (word = bytes per
+    vector element); none for moments from the Lanczos tridiagonal."""
+    Nd, nc, npl = int(info[0]), int(info[1]), int(info[2])
+    kr, quad = lanczos_run(info)
     per = Nd * nc ** 3 * 25 * word
-    return {"lanczos": K * per, "moments": ((npl + 1) // 2) * per, "stress": npl * per}
+    return {"lanczos": kr * per, "moments": 0 if quad else ((npl + 1) // 2) * per, "stress": npl * per}
 
 
 def hbm_bytes(info):
@@ -74,11 +85,12 @@ def hbm_bytes(info):
     hit the caches: the node's potential columns, its Gram entries at every
     recurrence step), except the moments, which every Fermi-level evaluation
     reads again (MU_EVALS, an upper bound: a converged search skips them)."""
-    Nd, nc, npl, K = int(info[0]), int(info[1]), int(info[2]), int(info[9])
+    Nd, nc, npl = int(info[0]), int(info[1]), int(info[2])
+    kr, quad = lanczos_run(info)
     gram = 12 * int(info[10])                      # value (8) + index pair (4)
     vloc = 8 * Nd
-    lan = {"lanczos": 8 * Nd * 2 * K + 4 * Nd + gram + vloc,
-           "moments": 8 * Nd * (npl + 1) + 32 * Nd + gram + vloc,
+    lan = {"lanczos": 8 * Nd * 2 * kr + 4 * Nd + gram + vloc,
+           "moments": (8 * Nd * (npl + 1) + 32 * Nd + (8 * Nd * 2 * kr + 4 * Nd if quad else gram + vloc)),
            "stress": 8 * Nd * (npl + 1) + 32 * Nd + 8 * Nd * 19 + gram + vloc}
     step = (lan["lanczos"] + lan["moments"] + lan["stress"] +
             8 * Nd * (npl + 1) * MU_EVALS +           # moments re-read by the Fermi-level search
@@ -120,6 +132,17 @@ def recorded_traffic(phase, precision, workload):
                         rec.get("workload") == workload and rec.get("source_sha1") == want:
                     return float(rec["bytes_per_launch"])
     return None
+
+
+def measured_hbm(bytes_per_launch, launch_ms):
+    """HBM rate of the dominant kernel from its recorded rocprofv3 traffic
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated) over its launch time; None
+    when no record matches the current kernel sources."""
+    if bytes_per_launch is None or not launch_ms:
+        return None
+    gbps = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    return {"bytes_per_launch": bytes_per_launch, "achieved": gbps, "frac": gbps / PEAK_HBM_GBPS,
+            "kind": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the dominant kernel, copy-calibrated"}
 
 
 def run_plan(sq, cells, precision, steps, warmup, **plan_kw):
@@ -288,7 +311,8 @@ def main():
         "hbm": {"achieved": hb_step / (r["ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": hb_step / (r["ms"] * 1e-3) / 1e9 / PEAK_HBM_GBPS,
                 "kind": "algorithmic (compulsory) bytes per step", "bytes_per_step": hb_step,
-                "dominant_kernel_bytes_per_launch": hb_launch[dom]},
+                "dominant_kernel_bytes_per_launch": hb_launch[dom],
+                "measured": measured_hbm(recorded_traffic(dom, head, wl), pl[dom])},
         "phases_ms": pl,
         "eager_ms_per_step": r.get("eager_ms", r["ms"]),
         "setup_s": r["setup_s"],

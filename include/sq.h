@@ -59,6 +59,14 @@ typedef enum {
 /* Working precision of the Chebyshev recurrence vectors (Sec. IV).  The
  * spectral-bound Lanczos, the moments' inner products, the coefficients, the
  * Fermi level and every reduction are FP64 in all modes.
+ *
+ * Moments: when every cell of the plan has max(K, ceil(npl / 2)) <= 63, the
+ * plan runs that many FP64 Lanczos steps per node and takes the moments
+ * rho_q^j, j <= npl, from the Lanczos tridiagonal (w^T p(H) w = e_1^T p(T) e_1
+ * for degree <= 2k after k steps; the bounds use the first K steps only).
+ * There is then no moments recurrence pass and the moments are FP64 in every
+ * mode.  Otherwise a recurrence pass on the cube forms them, in the
+ * precision below.
  *   SQ_FP64          FP64 vectors in both passes.
  *   SQ_MIXED         FP32 vectors in the moments pass and in the stress pass.
  *   SQ_MIXED_STRESS  FP64 vectors in the moments pass (so mu, rho and the
@@ -256,7 +264,7 @@ sq_status sq_moments(sq_plan plan, int cell, const int64_t* nodes, int64_t n, do
  * the steps taken), K = the cell's lanczos_steps.  Needs sq_density. */
 sq_status sq_lanczos(sq_plan plan, int cell, const int64_t* nodes, int64_t n, double* out);
 
-/* Plan queries (info has 12 entries): info[0] = N_d, info[1] = n_c,
+/* Plan queries (info has 14 entries): info[0] = N_d, info[1] = n_c,
  * info[2] = npl, info[3] = number of atom images, info[4] = max images in a
  * node tile, info[5..7] = largest number of images reaching one cube,
  * crossing one cube column, and nonzero at one node, info[8] = number of
@@ -265,7 +273,10 @@ sq_status sq_lanczos(sq_plan plan, int cell, const int64_t* nodes, int64_t n, do
  * info[10] = stored Gram-matrix entries over the cell's nodes (each read
  * at every recurrence step of its node: 12 bytes per entry), info[11] =
  * nodes whose Gram matrix is stored (one projector sweep per step; the
- * others take two). */
+ * others take two), info[12] = Lanczos steps run per node (K, or
+ * ceil(npl / 2) when more and the moments come from the tridiagonal),
+ * info[13] = 1 when the moments come from the Lanczos tridiagonal, 0 when
+ * from the recurrence pass. */
 sq_status sq_cell_info(sq_plan plan, int cell, int64_t* info);
 
 /* Device time of each phase accumulated over the calls since the last reset

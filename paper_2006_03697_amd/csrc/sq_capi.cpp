@@ -102,6 +102,9 @@ struct sq_plan_s {
   long long Ntot = 0;
   std::vector<CellDev> host_cells;   // what was uploaded to d_cells
   std::map<std::string, Tile> tuned; // autotuned tiles by key
+  // moments from the Lanczos tridiagonal (every cell: max(K, ceil(npl / 2))
+  // Lanczos steps fit one wave's components), else from the recurrence pass
+  bool qmom = false;
   std::string arch;
   std::string err;
 };
@@ -164,6 +167,10 @@ double box_dist2(const double* R, const double* lo, const double* hi) {
   }
   return d2;
 }
+
+// Lanczos steps whose tridiagonal fixes the moments up to degree npl
+// (degree <= 2k after k steps), and never fewer than the bounds use.
+int qmom_steps(const CellHost& c) { return std::max(c.K, (c.npl + 1) / 2); }
 
 sq_status build_cell(sq_plan p, const sq_cell& in, CellHost& c, int idx) {
   const std::string tag = "cell " + std::to_string(idx) + ": ";
@@ -512,7 +519,9 @@ sq_status enqueue_mu_rounds(sq_plan p, Selection* S, int rounds, hipStream_t s) 
 }
 
 // Bounds, moments, the Fermi level within its budget, coefficients and
-// density: no host interaction.
+// density: no host interaction.  The moments come from the Lanczos
+// tridiagonal when the plan runs enough Lanczos steps (qmom), else from the
+// recurrence pass on the cube.
 sq_status enqueue_density(sq_plan p, Selection* S, hipStream_t s) {
   const bool fp64 = p->opt.precision != SQ_MIXED;   // precision of the moments pass
   sq_status st = check_hip(p, sq_launch_fill_u32(p->P.err, 0u, 1, s), "clear");
@@ -525,10 +534,15 @@ sq_status enqueue_density(sq_plan p, Selection* S, hipStream_t s) {
   if (st == SQ_OK) st = check_hip(p, sq_launch_bounds(p->P, S->items, S->item_cell, S->nall, s), "bounds");
   phase_end(p, PH_BOUNDS, s);
   phase_begin(p, PH_MOMENTS, s);
-  for (const Group& g : S->groups)
+  if (p->qmom) {
     if (st == SQ_OK)
-      st = check_hip(p, sq_launch_moments(rec_launch(g, F_MOM), fp64, p->P, g.items, g.cell, g.n, s),
-                     "moments");
+      st = check_hip(p, sq_launch_qmoments(p->P, S->items, S->item_cell, S->nall, s), "moments");
+  } else {
+    for (const Group& g : S->groups)
+      if (st == SQ_OK)
+        st = check_hip(p, sq_launch_moments(rec_launch(g, F_MOM), fp64, p->P, g.items, g.cell, g.n, s),
+                       "moments");
+  }
   phase_end(p, PH_MOMENTS, s);
   phase_begin(p, PH_MU, s);
   if (st == SQ_OK)
@@ -697,7 +711,8 @@ sq_status autotune(sq_plan p) {
   bool dirty = false;
   for (Group& g : p->all.groups) {
     bool all_known = true;
-    for (int f = 0; f < F_N; ++f) all_known = all_known && p->tuned.count(tune_key(p, g, f)) > 0;
+    for (int f = 0; f < F_N; ++f)
+      all_known = all_known && ((f == F_MOM && p->qmom) || p->tuned.count(tune_key(p, g, f)) > 0);
     if (all_known) continue;
     const long long n = std::min<long long>(g.n, 2048);
     std::vector<Tile> cand;
@@ -710,6 +725,7 @@ sq_status autotune(sq_plan p) {
       }
     if (cand.size() < 2) continue;   // nothing to choose
     for (int f = 0; f < F_N && st == SQ_OK; ++f) {
+      if (f == F_MOM && p->qmom) continue;   // no recurrence pass for the moments
       if (f == F_STR)
         st = check_hip(p, sq_launch_fill_u32((unsigned*)p->P.coef, 0u,
                                              (long long)(2 * p->P.mstride) * p->Ntot, p->stream), "clear");
@@ -852,6 +868,8 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
   }
   const long long N = p->Ntot;
   PlanDev& P = p->P;
+  p->qmom = true;
+  for (const CellHost& c : p->cells) p->qmom = p->qmom && qmom_steps(c) <= SQ_KL_MAX - 1;
   P.mstride = npl_max + 2;
   P.inject = opt->inject;
   auto A = [&](size_t bytes) { return dalloc(p, bytes); };
@@ -895,6 +913,7 @@ sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_
     d.nc = c.nc;
     d.npl = c.npl;
     d.K = c.K;
+    d.krun = p->qmom ? qmom_steps(c) : c.K;
     d.nimg = (int)(c.img.size() / 4);
     d.nsp = (int)c.sp.size();
     d.mq = opt->cheb_quad_points;
@@ -1057,7 +1076,7 @@ sq_status sq_lanczos(sq_plan p, int cell, const int64_t* nodes, int64_t n, doubl
   for (int64_t i = 0; i < n; ++i) {
     if (nodes[i] < 0 || nodes[i] >= c.Nd) return fail(p, SQ_E_ARG, "node index out of range");
     double* o = out + (size_t)(2 * K + 1) * i;
-    const int ns = steps[nodes[i]];
+    const int ns = std::min(steps[nodes[i]], K);   // the steps the bounds use
     o[0] = ns;
     for (int k = 0; k < K; ++k) {
       o[1 + k] = k < ns ? lan[(size_t)W * nodes[i] + k] : 0.0;
@@ -1082,6 +1101,8 @@ sq_status sq_cell_info(sq_plan p, int cell, int64_t* info) {
   info[9] = c.K;
   info[10] = c.gram_entries;
   info[11] = c.gram_nodes;
+  info[12] = p->qmom ? qmom_steps(c) : c.K;
+  info[13] = p->qmom ? 1 : 0;
   return SQ_OK;
 }
 

@@ -35,7 +35,7 @@ struct CellDev {
   int nsp;
   int mq;             // Gauss-Chebyshev points of the coefficient integrals (0: per-node rule)
   int mu_mode;
-  int pad1;
+  int krun;           // Lanczos steps run: K, or ceil(npl / 2) when more and the moments come from them
   long long Nd, node_base;
   double h, dV, kT, ne, vol, mu0;
   double L[3];
@@ -122,6 +122,8 @@ hipError_t sq_launch_mu_eval(const PlanDev& P, const long long* items, const int
 hipError_t sq_launch_mu_step(const PlanDev& P, const int* cells, int ncells, hipStream_t s);
 hipError_t sq_launch_coeffs(const PlanDev& P, const long long* items, const int* item_cell,
                             long long nitems, hipStream_t s);
+hipError_t sq_launch_qmoments(const PlanDev& P, const long long* items, const int* item_cell,
+                              long long nitems, hipStream_t s);
 hipError_t sq_launch_stress(const RecLaunch& R, bool fp64, const PlanDev& P,
                             const long long* items, const int* item_cell, long long nitems,
                             hipStream_t s);

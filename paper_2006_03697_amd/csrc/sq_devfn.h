@@ -9,6 +9,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <utility>
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -33,6 +35,31 @@ __device__ __forceinline__ double sq_add(double s, double c) {
 __device__ __forceinline__ long long wrapll(long long i, long long n) {
   long long r = i % n;
   return r < 0 ? r + n : r;
+}
+
+// f(std::integral_constant<int, k>) for k = 0 .. N - 1, expanded in the
+// front end: a loop of large bodies indexed into register arrays stays
+// unrolled whatever the unroller's size limits.
+template <class F, int... K>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// The projector-slot loop: expanded in the front end up to 16 slots; wider
+// variants keep an unrolled loop (fully expanded, their register allocation
+// measured worse).
+template <int N, class F>
+__device__ __forceinline__ void slot_for(F&& f) {
+  if constexpr (N <= 16) {
+    static_for<N>(f);
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) f(k);
+  }
 }
 
 // Make a register value opaque to the optimiser (no hoisting of values

@@ -54,7 +54,8 @@ __global__ void k_bounds(PlanDev P, const long long* items, const int* item_cell
   if (it >= nitems) return;
   const long long g = items[it];
   const double* lan = P.lan + g * (2 * SQ_KL_MAX);
-  const int n = P.lan_steps[g];
+  // the first K steps (a longer run for the moments repeats them exactly)
+  const int n = min(P.lan_steps[g], P.cells[item_cell[it]].K);
   const double* a = lan;
   const double* b = lan + SQ_KL_MAX;
   double lo, hi;
@@ -557,6 +558,75 @@ hipError_t sq_launch_census(int nc, const PlanDev& P, const long long* items, co
   SQ_NC_LIST(SQ_CASE)
 #undef SQ_CASE
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev moments from the Lanczos tridiagonal.  k Lanczos steps from w_q
+// give the tridiagonal T (diagonal alpha_1..alpha_k, couplings
+// beta_1..beta_k) of H_q on the Krylov space of w_q; for every polynomial p
+// of degree <= 2k, w_q^T p(H_q) w_q = e_1^T p(T') e_1 with T' the
+// (k + 1) x (k + 1) extension of T (its last diagonal entry never enters at
+// that degree).  So rho^j = w_q^T T_j(Hhat_q) w_q = e_1^T T_j(That') e_1,
+// That' = (T' - chi_q) / zeta_q, for j <= npl <= 2k: the same moments as
+// the three-term recurrence on the cube (Sec. IV), from the small
+// recurrence t^{j+1} = 2 That' t^j - t^{j-1}, t^0 = e_1.  A Lanczos run that
+// stopped early found an invariant subspace, where the identity holds at
+// every degree.  One wave per node; lane i holds component i (k + 1 <= 64).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_qmoments(PlanDev P, const long long* items,
+                                                   const int* item_cell, long long nitems) {
+  const long long it = blockIdx.x * 4LL + (threadIdx.x >> 6);
+  if (it >= nitems) return;   // the whole wave
+  const int l = threadIdx.x & 63;
+  const long long g = items[it];
+  const int npl = P.cells[item_cell[it]].npl;
+  const double chi = P.bnd[4 * g + 2], zeta = P.bnd[4 * g + 3];
+  const int ns = P.lan_steps[g];
+  const double* lan = P.lan + g * (2 * SQ_KL_MAX);
+  // That': diagonal, coupling to the next and to the previous component
+  // (zero past the steps taken; the extension's diagonal entry is zero)
+  const double a = l < ns ? (lan[l] - chi) / zeta : 0.0;
+  const double b = l < ns ? lan[SQ_KL_MAX + l] / zeta : 0.0;
+  const double bp = __shfl_up(b, 1);
+  const double bl = l > 0 ? bp : 0.0;
+  auto apply = [&](double v) {
+    const double vu = __shfl_up(v, 1), vd = __shfl_down(v, 1);
+    return a * v + (bl * vu + b * vd);   // lane 0: bl = 0; lane 63: b = 0
+  };
+  double mj[2] = {0.0, 0.0};   // rho^j kept by lane j % 64 in slot j / 64
+  double t0 = l == 0 ? 1.0 : 0.0;
+  double t1 = apply(t0);
+  if (l == 0) mj[0] = 1.0;
+  {
+    const double r = __shfl(t1, 0);
+    if (l == 1) mj[0] = r;
+  }
+  for (int j = 2; j <= npl; ++j) {
+    const double t2 = 2.0 * apply(t1) - t0;
+    t0 = t1;
+    t1 = t2;
+    const double r = __shfl(t1, 0);
+    if (l == (j & 63)) mj[j >> 6] = r;
+  }
+  double* mom = P.mom + g * P.mstride;
+  bool bad = false;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = 64 * h + l;
+    if (j <= npl) {
+      mom[j] = mj[h];
+      if (!(fabs(mj[h]) <= 1.0 + 1e-6)) bad = true;   // as the recurrence kernel (FP64)
+    }
+  }
+  if (bad) atomicOr(P.err, SQ_ERR_BOUNDS);
+}
+
+hipError_t sq_launch_qmoments(const PlanDev& P, const long long* items, const int* item_cell,
+                              long long nitems, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_qmoments, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, P, items,
+                     item_cell, nitems);
+  return hipGetLastError();
 }
 
 hipError_t sq_launch_vloc(const CellDev* d_cell, const CellDev& h_cell, double* vloc, hipStream_t s) {

@@ -142,11 +142,18 @@ struct Var {
   static constexpr int GPT = (GCAP + NT - 1) / NT;   // Gram entries per thread (registers)
   static_assert(NIMG <= (1 << IBITS) && NIMG <= 65536, "image index width");
   static_assert(NT <= 1024, "workgroup size");
+  // The planes of a column are split into NSEG segments.  Per slot, a wave
+  // visits only the segments from the first to the last that the chord of
+  // some lane touches (images are sorted by z, so a slot holds images of
+  // similar height on every lane); the sweep then starts from the slot's
+  // weight at the first visited plane.  Only with the weights in registers.
+  static constexpr int NSEG = AREG_ && KC_ <= 16 && NC_ >= 13 ? 4 : 1;
+  __host__ __device__ static constexpr int seg_lo(int k) { return k * NC_ / NSEG; }
   // LDS besides the cube buffer: per-image tables, near images, block sums,
   // and a union of the projection sums (steps) with the stress pass's
   // near-image sums and line buffer (after the last step)
   static constexpr size_t OTHER = 8 * (size_t)NIMG * 9 + 8 * 4 * (size_t)NIMG + (size_t)NEAR * 12 +
-                                  2 * 2 * 16 * 8 + 256;
+                                  2 * 2 * 16 * 8 + 256 + 8 * (size_t)(NSEG - 1) * NIMG;
   static constexpr size_t EPB = 16 * (size_t)NEAR * 10 + 8 * 9 * (2 * SQ_FDM + 1);
   static constexpr size_t uni(int copies) {
     return 16 * (size_t)NIMG * copies > EPB ? 16 * (size_t)NIMG * copies : EPB;
@@ -178,6 +185,7 @@ struct Var {
                                : USED + uni(4) <= 163840 ? 4
                                : USED + uni(2) <= 163840 ? 2
                                                          : 1;
+  static_assert(USED + uni(NCOPY) <= 163840, "LDS");
 };
 
 template <class Vr>
@@ -192,6 +200,8 @@ struct Smem {
   // rq = (rr(0), cq) (one 16-byte read per slot and step)
   double e0[NI];
   typename Vec2<double>::type rq[NI];
+  // rr at the first plane of segments 1 .. NSEG - 1
+  double rrs[Vr::NSEG > 1 ? Vr::NSEG - 1 : 1][Vr::NSEG > 1 ? NI : 1];
   double pf[2][NI];                   // projections <chi_I, v>, double-buffered over steps
   double gpf[2][NI];                  // gamma dV <chi_I, v>
   union {
@@ -222,7 +232,11 @@ struct Ctx {
   // slot s: bit 31 - z set for the planes z of the chord of the image's
   // spherical support on this column; the image index in the low bits
   unsigned sid[Vr::KC];
-  double a0[Vr::AREG ? Vr::KC : 1];   // projector value of slot s at (cx, cy, plane 0)
+  // projector value of slot s at (cx, cy) on the first plane the wave visits
+  double a0[Vr::AREG ? Vr::KC : 1];
+  // wave-uniform segment range of slot s in bits 4(s % 8) of word s / 8:
+  // first segment in the low two bits, last segment in the next two
+  unsigned segw[Vr::NSEG > 1 ? (Vr::KC + 7) / 8 : 1];
   T vd[Vr::ZH];                       // diagonal of (H_q - shift) without the stencil centre
   // the node's stored Gram entries (global memory, read at every step)
   const double* gvp;
@@ -232,15 +246,21 @@ struct Ctx {
 };
 
 template <class Vr>
+__device__ __forceinline__ double plane0_weight(const Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C,
+                                                int i) {
+  constexpr int m = Vr::MH;
+  const double dx = node_coord(X.q0 + X.cx - m, C.h, S.ix[i]);
+  const double dy = node_coord(X.q1 + X.cy - m, C.h, S.iy[i]);
+  return exp(-sq_sum2(dx, dy) * S.i2s[i]) * S.e0[i];
+}
+
+template <class Vr>
 __device__ __forceinline__ double slot_start(const Smem<Vr>& S, const Ctx<Vr>& X, const CellDev& C,
                                              int s, int i) {
   if constexpr (Vr::AREG) {
     return X.a0[s];
   } else {
-    constexpr int m = Vr::MH;
-    const double dx = node_coord(X.q0 + X.cx - m, C.h, S.ix[i]);
-    const double dy = node_coord(X.q1 + X.cy - m, C.h, S.iy[i]);
-    return exp(-sq_sum2(dx, dy) * S.i2s[i]) * S.e0[i];
+    return plane0_weight<Vr>(S, X, C, i);
   }
 }
 
@@ -304,6 +324,17 @@ __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
   return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o);
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Stencil centre of the kinetic operator -1/2 Laplacian (three axes).
+__device__ __forceinline__ double node_diag_kinetic(const CellDev& C) {
+  return -0.5 / (C.h * C.h) * 3.0 * C.c2[0];
 }
 
 // Node prologue: image list of the cube (sorted by z, ties in gather order),
@@ -383,6 +414,17 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
     }
     S.e0[i] = e0;
     S.rq[i] = typename Vec2<double>::type{r0, cq};
+    if constexpr (Vr::NSEG > 1) {
+#pragma unroll
+      for (int k = 1; k < Vr::NSEG; ++k) {
+        double rk = 0.0;
+        if (i < nimg) {
+          const double uk = node_coord(X.q2 + Vr::seg_lo(k) - m, h, S.iz[i]);
+          rk = exp(-(2.0 * uk * h + h * h) * S.i2s[i]);
+        }
+        S.rrs[k - 1][i] = rk;
+      }
+    }
     S.pf[0][i] = 0.0;
     S.pf[1][i] = 0.0;
     S.gpf[0][i] = 0.0;
@@ -427,16 +469,48 @@ __device__ __forceinline__ void node_prologue(const CellDev& C, long long q, dou
       for (int s = 0; s < Vr::KC; ++s) {
         if (s == X.nslot) {
           X.sid[s] = word;
-          if constexpr (Vr::AREG) X.a0[s] = exp(-dxy2 * S.i2s[i]) * S.e0[i];
+          if constexpr (Vr::AREG) {
+            // with segments: the xy factor here, the z factor below
+            X.a0[s] = Vr::NSEG > 1 ? exp(-dxy2 * S.i2s[i]) : exp(-dxy2 * S.i2s[i]) * S.e0[i];
+          }
         }
       }
       ++X.nslot;
     }
   }
   X.nsw = wave_max(X.nslot);
+  if constexpr (Vr::NSEG > 1) {
+    constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
+#pragma unroll
+    for (int w = 0; w < (Vr::KC + 7) / 8; ++w) X.segw[w] = 0u;
+#pragma unroll
+    for (int s = 0; s < Vr::KC; ++s) {
+      // planes touched by slot s on any lane of the wave (bit 31 - z)
+      const unsigned u = wave_or(X.sid[s] & ~IMASK);
+      int kf = 0, kl = 0;
+      if (u != 0u) {
+        const int zf = __clz((int)u), zl = 31 - __builtin_ctz(u);
+#pragma unroll
+        for (int k = 1; k < Vr::NSEG; ++k) {
+          if (zf >= Vr::seg_lo(k)) kf = k;
+          if (zl >= Vr::seg_lo(k)) kl = k;
+        }
+      }
+      X.segw[s / 8] |= (unsigned)(kf | (kl << 2)) << (4 * (s % 8));
+      if (s < X.nslot) {
+        const int i = (int)(X.sid[s] & IMASK);
+        double e = S.e0[i];
+        if (kf > 0) {
+          const double uk = node_coord(X.q2 + Vr::seg_lo(kf) - m, h, S.iz[i]);
+          e = exp(-(uk * uk) * S.i2s[i]);
+        }
+        X.a0[s] *= e;
+      }
+    }
+  }
 
   // ---- diagonal: local potential (periodic) + stencil centre - shift ----
-  const double cdiag = -0.5 / (h * h) * 3.0 * C.c2[0];
+  const double cdiag = node_diag_kinetic(C);
   const long long ix = wrapll(X.q0 + X.cx - m, C.n[0]);
   const long long iy = wrapll(X.q1 + X.cy - m, C.n[1]);
 #pragma unroll
@@ -493,6 +567,42 @@ __device__ __forceinline__ void slot_sweep(unsigned mk, double a, typename Vec2<
   }
 }
 
+// Weights of slot s (image i, slot word mk, weight a on the first plane
+// visited) along the column, over the segments the wave visits for it:
+// f(z, on, w) is called for every plane of those segments.
+template <class Vr, class F>
+__device__ __forceinline__ void sweep(const Smem<Vr>& S, const Ctx<Vr>& X, int s, int i, unsigned mk,
+                                      double a, F f) {
+  const typename Vec2<double>::type rq = S.rq[i];
+  if constexpr (Vr::NSEG == 1) {
+    slot_sweep<Vr::ZH>(mk, a, rq, f);
+  } else {
+    const unsigned code = (X.segw[s / 8] >> (4 * (s % 8))) & 15u;   // uniform
+    const int kf = (int)(code & 3u), kl = (int)(code >> 2);
+    double rr = rq.x;
+    const double cq = rq.y;
+    if (kf > 0) {
+      rr = S.rrs[kf - 1][i];
+      mk <<= Vr::seg_lo(kf);
+    }
+#pragma unroll
+    for (int k = 0; k < Vr::NSEG; ++k) {
+      if (k >= kf && k <= kl) {
+#pragma unroll
+        for (int z = Vr::seg_lo(k); z < Vr::seg_lo(k + 1); ++z) {
+          unsigned nm;
+          const bool on = __builtin_add_overflow(mk, mk, &nm);   // bit 31 - z
+          mk = nm;
+          const double an = a * rr;
+          rr *= cq;
+          f(z, on, a);
+          a = an;
+        }
+      }
+    }
+  }
+}
+
 // Projections <chi_I, v> of the vector v held in registers, added to
 // S.pint (the caller places a barrier before they are read).
 template <class Vr>
@@ -500,18 +610,18 @@ __device__ __forceinline__ void project(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& 
                                         const typename Vr::T (&v)[Vr::ZH]) {
   using T = typename Vr::T;
   constexpr unsigned IMASK = (1u << Vr::IBITS) - 1u;
-#pragma unroll
-  for (int s = 0; s < Vr::KC; ++s) {
+  slot_for<Vr::KC>([&](auto si) __attribute__((always_inline)) {
+    const int s = si;
     if (s < X.nsw) {
       const unsigned mk = X.sid[s];
       const int i = (int)(mk & IMASK);
       T part = (T)0;
-      slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
-                         [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
+      sweep<Vr>(S, X, s, i, mk, slot_start<Vr>(S, X, C, s, i),
+                [&](int z, bool on, double a) { part += chord_weight<T>(on, a) * v[z]; });
       // a slot past the thread's count has sid 0 and weight zero: it adds 0 to image 0
       fx_add(S.pint[i][threadIdx.x & (Vr::NCOPY - 1)], (double)part, X.bad);
     }
-  }
+  });
 }
 
 // After the barrier that ends a step: the new projections
@@ -644,34 +754,33 @@ __device__ __forceinline__ void apply_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDe
   if constexpr (FUSED) {
     // (3) one sweep per image: projection of io, then the projector term
     // (a slot past the thread's count has sid 0: weight zero, image 0)
-#pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) {
+    slot_for<Vr::KC>([&](auto si) __attribute__((always_inline)) {
+      const int s = si;
       if (s < nsw) {
         const unsigned mk = X.sid[s];
         const int i = (int)(mk & IMASK);
         const T coef = (T)(sc * S.gpf[par][i]);
         T part = (T)0;
-        slot_sweep<ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
-                       [&](int z, bool on, double a) {
-                         const T w = chord_weight<T>(on, a);
-                         part += w * io[z];
-                         io[z] += w * coef;
-                       });
+        sweep<Vr>(S, X, s, i, mk, slot_start<Vr>(S, X, C, s, i), [&](int z, bool on, double a) {
+          const T w = chord_weight<T>(on, a);
+          part += w * io[z];
+          io[z] += w * coef;
+        });
         fx_add(S.pint[i][threadIdx.x & (Vr::NCOPY - 1)], (double)part, X.bad);
       }
-    }
+    });
   } else {
     // (3') the projector terms, then the projections of the finished io
-#pragma unroll
-    for (int s = 0; s < Vr::KC; ++s) {
+    slot_for<Vr::KC>([&](auto si) __attribute__((always_inline)) {
+      const int s = si;
       if (s < nsw) {
         const unsigned mk = X.sid[s];
         const int i = (int)(mk & IMASK);
         const double coef = s < X.nslot ? sc * S.gpf[par][i] : 0.0;
-        slot_sweep<ZH>(mk, coef * slot_start<Vr>(S, X, C, s, i), S.rq[i],
-                       [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
+        sweep<Vr>(S, X, s, i, mk, coef * slot_start<Vr>(S, X, C, s, i),
+                  [&](int z, bool on, double a) { io[z] += chord_weight<T>(on, a); });
       }
-    }
+    });
     project<Vr>(S, X, C, io);
   }
   __syncthreads();
@@ -961,15 +1070,21 @@ __device__ __forceinline__ void node_epilogue(const Ctx<Vr>& X, unsigned* err) {
 // (chi_q and zeta_q come from the extreme eigenvalues of H_q, Sec. IV)
 // ---------------------------------------------------------------------------
 // One Lanczos step with v_k in A (and S.tl), v_{k-1} in B on entry; on exit
-// v_{k+1} is in B (and S.tl) unless the recursion stopped.
+// v_{k+1} is in B (and S.tl) unless the recursion stopped.  The operator is
+// H_q - sigma (the node's diagonal entry, sigma = alpha_1): the same Krylov
+// space and couplings, alpha shifted by sigma, which is added back.  The
+// projections of v_{k+1} are (proj(H v_k - beta v_{k-1}) - alpha_k
+// proj(v_k)) / beta_k, so an error in proj(v_k) returns multiplied by
+// alpha_k / beta_k; unshifted that factor is about 2 at every step (errors
+// grow 1e5-fold in 20 steps, 1e11-fold in 40), shifted it stays below one.
 template <class Vr, bool FUSED>
 __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const CellDev& C,
                                              const double (&A)[Vr::ZH], double (&B)[Vr::ZH],
                                              const double* ck, int k, double& bprev, double& tol,
-                                             double* lan) {
+                                             double* lan, double sigma) {
   constexpr int ZH = Vr::ZH;
   constexpr int NW = Vr::NW;
-  apply_step<Vr, FUSED>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = H v_k - beta v_{k-1}
+  apply_step<Vr, FUSED>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = (H - sigma) v_k - beta v_{k-1}
   double a = 0.0, dum = 0.0;
 #pragma unroll
   for (int z = 0; z < ZH; ++z) a += A[z] * B[z];
@@ -983,10 +1098,10 @@ __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const Cell
   block_sum2_db<NW>(b, dum, S.red[1]);
   b = sqrt(b);
   if (threadIdx.x == 0) {
-    lan[k] = a;
+    lan[k] = a + sigma;
     lan[SQ_KL_MAX + k] = b;
   }
-  if (k == 0) tol = 1e-14 * (fabs(a) + b);
+  if (k == 0) tol = 1e-14 * (fabs(a + sigma) + b);
   if (b < tol) return false;
   const double ib = 1.0 / b;
 #pragma unroll
@@ -1009,8 +1124,10 @@ __global__ void __launch_bounds__(Vr::NT) k_lanczos(PlanDev P, const long long* 
   for_nodes<Vr, PERSIST>(S, items, item_cell, nitems, counter, [&](long long g, int ci) __attribute__((always_inline)) {
     const CellDev& C = P.cells[ci];
     const long long q = g - C.node_base;
+    // the diagonal entry of H_q at the node (the prologue's diagonal there)
+    const double sigma = C.vloc[q] + node_diag_kinetic(C);
     Ctx<Vr> X;
-    node_prologue<Vr>(C, q, 0.0, S, X, P.err);
+    node_prologue<Vr>(C, q, sigma, S, X, P.err);
     if constexpr (FUSED) gram_load<Vr>(X, P, g);
     double ck[SQ_FDM + 1];
     stencil_coefs<double>(C, ck);
@@ -1019,12 +1136,12 @@ __global__ void __launch_bounds__(Vr::NT) k_lanczos(PlanDev P, const long long* 
     double bprev = 0.0, tol = 0.0;
     int steps = 0;
     double* lan = P.lan + g * (2 * SQ_KL_MAX);
-    for (int k = 0; k < C.K; k += 2) {
+    for (int k = 0; k < C.krun; k += 2) {
       steps = k + 1;
-      if (!lanczos_step<Vr, FUSED>(S, X, C, A, B, ck, k, bprev, tol, lan)) break;
-      if (k + 1 >= C.K) break;
+      if (!lanczos_step<Vr, FUSED>(S, X, C, A, B, ck, k, bprev, tol, lan, sigma)) break;
+      if (k + 1 >= C.krun) break;
       steps = k + 2;
-      if (!lanczos_step<Vr, FUSED>(S, X, C, B, A, ck, k + 1, bprev, tol, lan)) break;
+      if (!lanczos_step<Vr, FUSED>(S, X, C, B, A, ck, k + 1, bprev, tol, lan, sigma)) break;
     }
     if (threadIdx.x == 0) P.lan_steps[g] = steps;
     node_epilogue<Vr>(X, P.err);
@@ -1212,7 +1329,8 @@ __device__ __forceinline__ void near_sums(Smem<Vr>& S, Ctx<Vr>& X, const CellDev
       if (nidx >= 0) {
         const double rx = xc - S.ix[i], ry = yc - S.iy[i];
         double acc[3] = {0.0, 0.0, 0.0};
-        slot_sweep<Vr::ZH>(mk, slot_start<Vr>(S, X, C, s, i), S.rq[i],
+        // once per node: the whole column from plane 0
+        slot_sweep<Vr::ZH>(mk, plane0_weight<Vr>(S, X, C, i), S.rq[i],
                            [&](int z, bool on, double chiv) {
                              if (on) {
                                if constexpr (DIR < 0) {

@@ -220,7 +220,7 @@ class Plan:
         self.h = handle
         self.info = []
         for i in range(len(self.cells)):
-            inf = np.zeros(12, dtype=np.int64)
+            inf = np.zeros(14, dtype=np.int64)
             self._check(self.L.sq_cell_info(self.h, i, _i64(inf)), "sq_cell_info")
             self.info.append(inf)
 

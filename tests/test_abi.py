@@ -109,7 +109,7 @@ def test_bench_algorithmic_counts():
     import sys
     sys.path.insert(0, ROOT)
     import bench
-    info = [64000, 21, 60, 0, 0, 0, 0, 0, 1000, 20, 5000, 64000]
+    info = [64000, 21, 60, 0, 0, 0, 0, 0, 1000, 20, 5000, 64000, 20, 0]
     pts = 64000 * 21 ** 3
     f = bench.kernel_flops(info)
     assert f["stress"] == 60 * (78 * pts + 4 * 1000)
@@ -123,5 +123,15 @@ def test_bench_algorithmic_counts():
     assert per["stress"] == 8 * 64000 * 61 + 32 * 64000 + 8 * 64000 * 19 + 12 * 5000 + 8 * 64000
     # every Fermi-level evaluation re-reads the moments
     assert step > bench.MU_EVALS * 8 * 64000 * 61
+    # moments from the Lanczos tridiagonal: 30 Lanczos steps, no moments pass
+    quad = info[:12] + [30, 1]
+    fq = bench.kernel_flops(quad)
+    assert fq["lanczos"] == 30 * (86 * pts + 4 * 1000)
+    assert fq["moments"] == 64000 * 60 * 7 * 31
+    assert bench.lds_bytes(quad, 8)["moments"] == 0
     # a traffic record is used only for the kernel sources it was taken on
     assert bench.recorded_traffic("stress", "fp64", "no such workload") is None
+    # measured HBM rate: recorded bytes per launch over the launch time
+    assert bench.measured_hbm(None, 100.0) is None
+    m = bench.measured_hbm(8e9, 1000.0)
+    assert abs(m["achieved"] - 8.0) < 1e-12 and abs(m["frac"] - 1e-3) < 1e-15
