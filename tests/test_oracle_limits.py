@@ -11,7 +11,12 @@ constants (CPU only):
 * the stress as the strain derivative of the grand potential (Sec. II): a
   finite difference of the Gamma-point grand potential of a strained
   periodic cell, from dense diagonalisation, against the oracle's kinetic +
-  nonlocal stress plus the local-potential term.
+  nonlocal stress plus the local-potential term;
+* the infinite-cell reading with atoms (Sec. IV, infinite cell; App. B):
+  the density of truncated cubes with every atom image its own projector
+  converges, as R_cut grows, to the Brillouin-zone integral of the Bloch
+  Hamiltonians of the periodic crystal (dense diagonalisation on a k-grid),
+  not to the Gamma-point density of the periodic cell.
 """
 
 import math
@@ -316,3 +321,69 @@ def test_stress_is_the_strain_derivative_of_the_grand_potential():
     # entry), so an a <-> b transposition of its gradient term would move
     # sigma by ~1e-9: invisible here, and harmless
     assert np.max(np.abs(N - N.T)) < 3e-6 * np.max(np.abs(N))
+
+
+# ----------------------------------------------------------------------------
+# k-points: the infinite crystal against the Gamma point
+# ----------------------------------------------------------------------------
+
+def _bloch_density(cell, kv, mu, kT):
+    """rho = (2 / dV) diag f(H(k)) of the Bloch Hamiltonian H(k) of the
+    periodic FD crystal on the cell's grid: psi(x + L) = e^{i k.L} psi(x)
+    gives the stencil a phase where it leaves the cell, and the projectors
+    of all images of an atom combine into B(x) = sum_L chi(x - R - L) e^{i k.L},
+    with V_nl(k) = gamma dV sum_R |B><B|."""
+    n = int(round(cell["L"][0] / cell["h"]))
+    h, L = cell["h"], cell["L"][0]
+    sp = cell["species_params"][0] if "species_params" in cell else W.GAUSS_SPECIES
+    c2, _ = O.fd_weights(6)
+    idx = np.arange(n ** 3)
+    g3 = np.stack([idx % n, (idx // n) % n, idx // (n * n)], 1)
+    X = g3 * h
+    dV = h ** 3
+    H = np.zeros((n ** 3, n ** 3), complex)
+    for a in range(3):
+        for m in range(-6, 7):
+            t = g3[:, a] + m
+            wrap = np.floor_divide(t, n)
+            j3 = g3.copy()
+            j3[:, a] = t - wrap * n
+            j = j3[:, 0] + n * (j3[:, 1] + n * j3[:, 2])
+            np.add.at(H, (idx, j), -0.5 / h ** 2 * c2[abs(m)] * np.exp(1j * kv[a] * wrap * L))
+    V = np.zeros(n ** 3)
+    shifts = np.array([(i, j, k) for i in range(-3, 4) for j in range(-3, 4) for k in range(-3, 4)], float)
+    for R in np.asarray(cell["pos"]):
+        B = np.zeros(n ** 3, complex)
+        for s in shifts:
+            d2 = np.sum((X - (R + s * L)) ** 2, 1)
+            V += np.where(d2 < sp["v_rcut"] ** 2, -sp["v_amp"] * np.exp(-d2 / (2 * sp["v_sigma"] ** 2)), 0.0)
+            B += (np.where(d2 < sp["p_rcut"] ** 2, np.exp(-d2 / (2 * sp["p_sigma"] ** 2)), 0.0) *
+                  np.exp(1j * (kv @ (s * L))))
+        H += sp["gamma"] * dV * np.outer(B, B.conj())
+    H[idx, idx] += V
+    lam, U = np.linalg.eigh(H)
+    return 2.0 / dV * np.sum(np.abs(U) ** 2 * _fermi(lam, mu, kT), 1)
+
+
+def test_infinite_cell_density_reaches_the_brillouin_zone_limit():
+    # 6 Bohr cell, h 0.6 (10^3 nodes), two atoms, kT 1 Ha, fixed mu: the
+    # Gamma-point density differs from the infinite crystal's by ~6e-5 (the
+    # periodic images of the cell are too close), the truncated cubes of
+    # R_cut 3, 4, 5 Bohr approach the k-integrated density exponentially
+    kT, mu = 1.0, 0.5
+    base = W.random_cell(seed=0, L=6.0, h=0.6, n_atoms=2, d_min=2.0, rcut=3.0, npl=160, kT=kT,
+                         mu_mode="fixed", mu=mu, n_electrons=0.0)
+    L = 6.0
+    ks = np.array([-0.25, 0.25])   # 2^3 grid without Gamma: its own error is below 1e-8 here
+    rho_bz = np.mean([_bloch_density(base, 2 * np.pi / L * np.array([a, b, c]), mu, kT)
+                      for a in ks for b in ks for c in ks], axis=0)
+    rho_g = _bloch_density(base, np.zeros(3), mu, kT)
+    gap = np.max(np.abs(rho_g - rho_bz))
+    errs = []
+    for rc in (3.0, 4.0, 5.0):
+        r = O.run(dict(base, rcut=rc), with_stress=False)
+        errs.append(np.max(np.abs(r["rho"] - rho_bz)))
+    print("Gamma vs BZ %.2e; cube R_cut 3/4/5 vs BZ %s" % (gap, " ".join("%.2e" % e for e in errs)))
+    assert gap > 2e-5
+    assert errs[0] > 5 * errs[1] > 25 * errs[2]
+    assert errs[2] < 1e-7 and errs[2] < gap / 100
