@@ -28,6 +28,9 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
 HEADERS = [os.path.join(INCLUDE, "sq.h"), os.path.join(INCLUDE, "sq_probe.h"), os.path.join(CSRC, "sq_dev.h"),
            os.path.join(CSRC, "sq_devfn.h")]
 
+# roctx ranges over the entry points (rocprofv3 --marker-trace)
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
 NC_LIST = [7, 9, 11, 13, 15, 17, 19, 21, 23, 25]
 # (source, device code?, extra defines, object name)
 UNITS = [("sq_misc.hip", True, [], "sq_misc.o"), ("sq_capi.cpp", False, [], "sq_capi.o"),
@@ -79,7 +82,7 @@ def build(verbose: bool = False, jobs: int = 0, lib: str = LIB, build_dir: str =
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(one, units))
     tmp = lib + ".tmp"
-    _run([HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp] + objs)
+    _run([HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp] + objs + LINK)
     os.replace(tmp, lib)
     if verbose:
         print("built %s in %.1fs" % (lib, time.time() - t0))

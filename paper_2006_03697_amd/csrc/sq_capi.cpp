@@ -18,6 +18,8 @@
 #include "sq.h"
 #include "sq_dev.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 namespace {
 
 struct CellHost {
@@ -110,6 +112,16 @@ struct sq_plan_s {
 };
 
 namespace {
+
+// A roctx range over one entry point (host wall time, with its final
+// synchronisation): rocprofv3 --marker-trace shows the calls beside the
+// kernels they launch.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // Fermi-level evaluations launched back to back in every sq_density before
 // the host looks at the search state; a search still running after them
@@ -830,6 +842,7 @@ void sq_destroy(sq_plan plan) {
 }
 
 sq_status sq_setup(const sq_cell* cells, int n_cells, const sq_options* opt, sq_plan* out) {
+  Range range_("sq_setup");
   if (!out) return fail(nullptr, SQ_E_ARG, "out is NULL");
   *out = nullptr;
   if (!cells || n_cells < 1 || !opt) return fail(nullptr, SQ_E_ARG, "cells / options missing");
@@ -1120,6 +1133,7 @@ sq_status sq_phase_times(sq_plan p, int reset, double* ms, int64_t* count) {
 }
 
 sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
+  Range range_("sq_density");
   if (!p) return SQ_E_ARG;
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
@@ -1199,6 +1213,7 @@ sq_status sq_density(sq_plan p, int cell, double* rho, double* mu) {
 }
 
 sq_status sq_energy(sq_plan p, int cell, double* e_band) {
+  Range range_("sq_energy");
   if (!p) return SQ_E_ARG;
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
@@ -1219,6 +1234,7 @@ sq_status sq_energy(sq_plan p, int cell, double* e_band) {
 }
 
 sq_status sq_stress(sq_plan p, int cell, double* sigma_voigt, double* parts) {
+  Range range_("sq_stress");
   if (!p) return SQ_E_ARG;
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
@@ -1230,6 +1246,7 @@ sq_status sq_stress(sq_plan p, int cell, double* sigma_voigt, double* parts) {
 }
 
 sq_status sq_stress_static(sq_plan p, int cell, double* sigma_voigt, double* parts) {
+  Range range_("sq_stress_static");
   if (!p) return SQ_E_ARG;
   if ((int)p->cells.size() > SQ_STATIC_CELLS)
     return fail(p, SQ_E_ARG, "sq_stress_static: the plan has " + std::to_string(p->cells.size()) +
@@ -1258,6 +1275,7 @@ sq_status sq_stress_static(sq_plan p, int cell, double* sigma_voigt, double* par
 }
 
 sq_status sq_pressure(sq_plan p, int cell, double* p_direct, double* p_trace) {
+  Range range_("sq_pressure");
   if (!p) return SQ_E_ARG;
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);
@@ -1297,6 +1315,7 @@ sq_status sq_pressure(sq_plan p, int cell, double* p_direct, double* p_trace) {
 }
 
 sq_status sq_xc(sq_plan p, int cell, double* e_xc, double* sigma_xc) {
+  Range range_("sq_xc");
   if (!p) return SQ_E_ARG;
   Selection* S = nullptr;
   sq_status st = select(p, cell, &S);

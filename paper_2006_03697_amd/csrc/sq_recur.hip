@@ -1085,17 +1085,28 @@ __device__ __forceinline__ bool lanczos_step(Smem<Vr>& S, Ctx<Vr>& X, const Cell
   constexpr int ZH = Vr::ZH;
   constexpr int NW = Vr::NW;
   apply_step<Vr, FUSED>(S, X, C, A, B, ck, 1.0, bprev, k & 1);   // B = (H - sigma) v_k - beta v_{k-1}
-  double a = 0.0, dum = 0.0;
-#pragma unroll
-  for (int z = 0; z < ZH; ++z) a += A[z] * B[z];
-  block_sum2_db<NW>(a, dum, S.red[0]);
-  double b = 0.0;
+  // alpha = <v_k, B> and |B|^2 in one block sum: |B - alpha v_k|^2 =
+  // |B|^2 - alpha^2 for a unit v_k.  With the shift alpha is not large
+  // against beta, so the difference keeps its accuracy; where it cancels
+  // (beta^2 < 1e-4 |B|^2, near an invariant subspace) the residual's norm
+  // is summed directly.
+  double a = 0.0, bb = 0.0;
 #pragma unroll
   for (int z = 0; z < ZH; ++z) {
-    B[z] -= a * A[z];
-    b += B[z] * B[z];
+    a += A[z] * B[z];
+    bb += B[z] * B[z];
   }
-  block_sum2_db<NW>(b, dum, S.red[1]);
+  block_sum2_db<NW>(a, bb, S.red[0]);
+  double b = bb - a * a;
+#pragma unroll
+  for (int z = 0; z < ZH; ++z) B[z] -= a * A[z];
+  if (!(b > 1e-4 * bb)) {   // uniform
+    double dum = 0.0;
+    b = 0.0;
+#pragma unroll
+    for (int z = 0; z < ZH; ++z) b += B[z] * B[z];
+    block_sum2_db<NW>(b, dum, S.red[1]);
+  }
   b = sqrt(b);
   if (threadIdx.x == 0) {
     lan[k] = a + sigma;
