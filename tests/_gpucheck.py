@@ -1,6 +1,20 @@
-"""Comparison helpers shared by the GPU parity tests."""
+"""Comparison and reporting helpers shared by the GPU parity tests."""
+
+import os
+import sys
 
 import numpy as np
+
+
+def report(*a):
+    """A line of the parity report: to stderr, and appended to
+    $SQ_REPORT_DIR/parity_report.txt when that variable names a folder."""
+    print(*a, file=sys.stderr, flush=True)
+    d = os.environ.get("SQ_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, "parity_report.txt"), "a") as f:
+            print(*a, file=f)
 
 
 def moments_excess(mom, lo, hi, ref):

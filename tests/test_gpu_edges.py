@@ -16,13 +16,11 @@ C ABI), each checked against the FP64 CPU oracle on every node:
 
 import ctypes
 import math
-import os
-import sys
 
 import numpy as np
 import pytest
 
-from _gpucheck import moments_excess
+from _gpucheck import moments_excess, report
 from oracle import oracle as O
 from paper_2006_03697_amd import workloads as W
 
@@ -32,10 +30,7 @@ TOL64 = 1e-10
 
 
 def _log(*a):
-    print(*a, file=sys.stderr, flush=True)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity_report.txt"), "a") as f:
-        print(*a, file=f)
+    report(*a)
 
 
 @pytest.fixture(scope="module")

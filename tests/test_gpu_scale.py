@@ -19,14 +19,12 @@ whole-cell comparison pins to the oracle's own.
 """
 
 import math
-import os
-import sys
 import time
 
 import numpy as np
 import pytest
 
-from _gpucheck import moments_excess
+from _gpucheck import moments_excess, report
 from oracle import oracle as O
 from paper_2006_03697_amd import workloads as W
 
@@ -37,10 +35,7 @@ TOL_MIXED_SIGMA = 1e-6   # Ha/Bohr^3, absolute, every Voigt component
 
 
 def _log(*a):
-    print(*a, file=sys.stderr, flush=True)
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "parity_report.txt"), "a") as f:
-        print(*a, file=f)
+    report(*a)
 
 
 @pytest.fixture(scope="module")
