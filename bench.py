@@ -154,11 +154,13 @@ def run_plan(sq, cells, precision, steps, warmup, **plan_kw):
     setup_s = time.time() - t0
     info = [i.copy() for i in plan.info]
 
+    last = {}
+
     def step():
-        plan.density_only(-1)
+        last["mu"] = plan.density_only(-1)
         plan.energy(-1)
-        plan.stress(-1)
-        plan.pressure(-1)
+        last["sig"], _ = plan.stress(-1)
+        last["pd"], last["pt"] = plan.pressure(-1)
         plan.xc(-1)
 
     label = "%d cell%s, %d nodes, %s" % (len(cells), "" if len(cells) == 1 else "s",
@@ -178,9 +180,7 @@ def run_plan(sq, cells, precision, steps, warmup, **plan_kw):
         if steps <= 3 or times[-1] > 5.0:
             print("bench:   step %d (%s): %.2f s" % (k, label, times[-1]), file=sys.stderr, flush=True)
     ph = plan.phase_times(reset=True)
-    _, mu = plan.density(-1)
-    sig, _ = plan.stress(-1)
-    pd, pt = plan.pressure(-1)
+    mu, sig, pd, pt = last["mu"], last["sig"], last["pd"], last["pt"]   # of the last timed step
     plan.close()
     times.sort()
     ms = 1000.0 * times[len(times) // 2]   # median step
@@ -334,13 +334,15 @@ def main():
 
     if args.extra:
         tune = os.path.join(tempfile.gettempdir(), "sq_bench_tune.json")
+        # the batch: one warm-up (it captures the graphs) and one timed step;
+        # the 512000-node cell: one eager step (40 s; launch overhead is nil)
         extra = {"batched_32_cells": (W.batched_cells(n_cells=32, seed=3),
-                                      dict(use_graph=graph, autotune=True, tune_cache=tune)),
-                 "large_512000_nodes": ([W.large_cell()], dict(use_graph=graph))}
-        for name, (cells, kw) in extra.items():
+                                      dict(use_graph=graph, autotune=True, tune_cache=tune), 1),
+                 "large_512000_nodes": ([W.large_cell()], dict(use_graph=False), 0)}
+        for name, (cells, kw, warm) in extra.items():
             e = {}
             for prec in ("fp64", "mixed"):
-                x = run_plan(sq, cells, prec, 1, 1, **kw)
+                x = run_plan(sq, cells, prec, 1, warm, **kw)
                 e[prec] = {"value": x["nodes"] / (x["ms"] * 1e-3), "ms_per_step": x["ms"],
                            "setup_s": x["setup_s"]}
                 print("bench: %s %s %.1f ms/step (set-up %.1f s)" % (name, prec, x["ms"], x["setup_s"]),
@@ -353,8 +355,10 @@ def main():
                 e["nodes"] = x["nodes"]
             e["speedup_mixed_vs_fp64"] = e["fp64"]["ms_per_step"] / e["mixed"]["ms_per_step"]
             e["unit"] = "node-columns/s"
-            e["launch"] = ("graph replay" if graph else "eager") + (", autotuned" if kw.get("autotune") else "")
+            e["launch"] = ("graph replay" if kw.get("use_graph") else "eager") + \
+                (", autotuned" if kw.get("autotune") else "")
             e["steps"] = 1
+            e["warmup"] = warm
             out[name] = e
 
     if args.cpu_sample > 0:

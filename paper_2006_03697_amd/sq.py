@@ -248,8 +248,10 @@ class Plan:
         return out, mu
 
     def density_only(self, cell: int = -1):
-        """sq_density without copying rho (timing)."""
-        self._check(self.L.sq_density(self.h, cell, None, None), "sq_density")
+        """sq_density without copying rho (timing); returns mu per cell."""
+        mu = np.zeros(len(self._cells(cell)))
+        self._check(self.L.sq_density(self.h, cell, None, _dp(mu)), "sq_density")
+        return mu
 
     def energy(self, cell: int = -1) -> np.ndarray:
         e = np.zeros(len(self._cells(cell)))
