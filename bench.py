@@ -325,7 +325,9 @@ def main():
         mf = kernel_flops(m["info"][0], stress_fp64=False)
         mpl = per_launch(m)
         out[mk] = {"value": Nd / (m["ms"] * 1e-3), "ms_per_step": m["ms"], "dtype": "f32+f64",
-                   "vectors": "f32 both passes" if mk == "mixed" else "f64 moments, f32 stress pass",
+                   "vectors": ("f64 moments from the Lanczos tridiagonal, f32 stress pass"
+                               if lanczos_run(m["info"][0])[1] else
+                               "f32 both passes" if mk == "mixed" else "f64 moments, f32 stress pass"),
                    "speedup_vs_fp64": r["ms"] / m["ms"], "phases_ms": mpl,
                    "stress_tflops": mf["stress"] / (mpl["stress"] * 1e-3) / 1e12,
                    "mu_diff_vs_fp64": abs(m["mu"][0] - r["mu"][0]),
